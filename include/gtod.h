@@ -1,0 +1,315 @@
+/*
+ * gtod.h -- C-ABI of the MI355X (gfx950) time-ordered-data simulator.
+ *
+ * The library simulates what a ground-based submillimetre IFU with kinetic
+ * inductance detectors records (arXiv 2604.23305, section 2): for every
+ * time sample t, spatial pixel p and frequency bin nu it samples the
+ * moving PWV screen at the pixel's pointing, interpolates the zenith
+ * transmission table and applies the airmass, propagates source plus sky
+ * through the radiative-transfer cascade, contracts over frequency with the
+ * channel responses to get the power per channel, and adds photon (white)
+ * noise and 1/f (pink) noise.  Output: P_tot[p][k][t] in watts.
+ *
+ * Conventions for every call
+ *   - Every call returns a gtod_status: 0 on success, a negative code on
+ *     failure.  gtod_last_error() gives a message for the last failure on
+ *     a context.
+ *   - Angles are radians, frequencies Hz, temperatures K, PWV mm, spectral
+ *     powers W/Hz, powers W.
+ *   - "host" pointers are read during the call only; the caller keeps
+ *     ownership and may free them on return.  "device" pointers are
+ *     caller-owned device memory on the context's GPU that must stay valid
+ *     until the stream passed to gtod_simulate_tod has passed the call.
+ *   - A context is used by one host thread at a time.
+ *   - Descriptors are validated before anything is enqueued: a failed call
+ *     leaves no partial work behind.
+ */
+#ifndef GTOD_H
+#define GTOD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t gtod_status;
+#define GTOD_OK 0
+#define GTOD_EINVAL (-1)        /* bad argument, shape or descriptor      */
+#define GTOD_ENOMEM (-2)        /* device allocation failed               */
+#define GTOD_EBUDGET (-3)       /* would exceed the context's HBM budget  */
+#define GTOD_ENOTFOUND (-4)     /* unknown screen / spectral id           */
+#define GTOD_ERANGE (-5)        /* pointing leaves the screen or the PWV
+                                   leaves the table (STRICT_RANGE only)   */
+#define GTOD_EDEVICE (-6)       /* HIP runtime error                      */
+#define GTOD_EUNSUPPORTED (-7)  /* device is not gfx950                   */
+
+typedef struct gtod_ctx gtod_ctx;
+
+/* contraction precision */
+#define GTOD_PREC_FP32 0        /* FP32 MFMA, FP32 accumulation          */
+#define GTOD_PREC_SPLIT_BF16 1  /* hi+lo BF16 MFMA, FP32 accumulation    */
+
+/* init flags */
+#define GTOD_INIT_STRICT_RANGE 1u
+
+/*
+ * gtod_sim_init -- create a context on one GPU.
+ *
+ * The fixed telescope and detector parameters of section 2.3 live here:
+ * taper, Ruze surface and polarisation efficiencies act on the source at
+ * stage 0 (section 2.5); the superconducting gap Delta and pair-breaking
+ * efficiency eta_pb enter the photon-noise NEP (section 2.6) and the
+ * low-frequency cutoff h nu < 2 Delta; T_CMB is the blackbody behind the
+ * source; f_sample converts NEP to the white-noise sigma.
+ *
+ * hbm_budget_bytes caps everything the context allocates (resident
+ * screens, spectral tables and per-stream workspaces); 0 means 90% of the
+ * free device memory.  workspace_bytes sizes each stream's scratch
+ * (frequency panel and 1/f FFT scratch); 0 picks 1 GiB.
+ *
+ * Errors: EINVAL (NULL pointers, non-positive f_sample), EUNSUPPORTED
+ * (not gfx950), EDEVICE, ENOMEM/EBUDGET (workspace).  *out is NULL on
+ * failure.  Free the context with gtod_free(ctx, GTOD_OBJ_CTX, 0).
+ */
+typedef struct gtod_init_desc {
+  int32_t device;
+  int32_t precision;          /* default for jobs that pass -1            */
+  uint32_t flags;             /* GTOD_INIT_*                              */
+  int32_t reserved0;
+  uint64_t hbm_budget_bytes;
+  uint64_t workspace_bytes;
+  double f_sample_hz;
+  double eta_taper;           /* eta_t                                    */
+  double rho_surf_m;          /* rms surface roughness for Ruze           */
+  double eta_pol;             /* 0.5 for a single-polarisation detector  */
+  double delta_J;             /* superconducting gap energy, J            */
+  double eta_pb;              /* pair-breaking efficiency                 */
+  double t_cmb_K;
+} gtod_init_desc;
+
+gtod_status gtod_sim_init(const gtod_init_desc* desc, gtod_ctx** out);
+
+/*
+ * gtod_load_screen -- make a PWV screen resident (section 2.2 and Eq.
+ * xy_atm).  pwv_mm is [ny][nx] FP64, x contiguous; x is the wind axis.
+ * Grid index of a screen position: gx = x/dx_m + ix0, gy = y/dy_m + iy0.
+ * The screen moves with wind_mps along +x; h_column_m is the height of
+ * the water-vapour column.  Bilinear sampling; positions outside the grid
+ * take the edge value and are counted (gtod_get_counters), or fail the
+ * simulate call with ERANGE when the context is STRICT_RANGE and the scan
+ * is analytic.
+ *
+ * mem_kind 0: pwv_mm is host memory; 1: device memory.  The data are
+ * deep-copied into library-owned memory charged to the budget; the call
+ * is synchronous.  nx, ny >= 2.
+ * Errors: EINVAL, EBUDGET, ENOMEM, EDEVICE.
+ */
+typedef struct gtod_screen_desc {
+  const double* pwv_mm;
+  int64_t nx, ny;
+  double dx_m, dy_m, ix0, iy0;
+  double h_column_m;
+  double wind_mps;
+  int32_t mem_kind;
+  int32_t reserved0;
+} gtod_screen_desc;
+
+gtod_status gtod_load_screen(gtod_ctx* ctx, const gtod_screen_desc* desc,
+                             int32_t* id);
+
+/* optics stage kinds (stages after the atmosphere, section 2.5) */
+#define GTOD_STAGE_REFLECT 0      /* eta(nu), couples to P_JN(t_K)        */
+#define GTOD_STAGE_ATM_COUPLED 1  /* eta(nu), couples to the sky:
+                                     (1-eta_atm) P_JN(T_atm)
+                                     + eta_atm P_JN(T_CMB)               */
+#define GTOD_STAGE_OHMIC 2        /* eta = 1 - eps_ref sqrt(nu/nu_ref)    */
+#define GTOD_STAGE_REFRACTIVE 3   /* surface (t_refl_K), absorption
+                                     exp(-2 pi d n tan(delta)/lambda)
+                                     (t_K), surface; AR coating keeps only
+                                     the absorbing pass                   */
+typedef struct gtod_stage {
+  int32_t kind;
+  int32_t ar_coated;
+  const double* eta;          /* host [F] or NULL to use eta_const        */
+  double eta_const;
+  double t_K;
+  double t_refl_K;
+  double eps_ref, nu_ref_hz;
+  double d_m, n_index, tan_delta;
+} gtod_stage;
+
+/* channel-response modes (section 2.3) */
+#define GTOD_FILT_LORENTZ 0     /* eta_peak / (1 + 4R^2 (nu/f - 1)^2)      */
+#define GTOD_FILT_FILTERBANK 1  /* numerator eta_peak minus the responses
+                                   of all upstream channels (strictly
+                                   higher f; equal f: lower index first)  */
+#define GTOD_FILT_MATRIX 2      /* user curves eta_filt[F][K]             */
+
+/*
+ * gtod_load_filters -- make the whole frequency-dimensional instrument
+ * resident and precompute its tables on the device (FP64).
+ *
+ * nu_hz[F], w_hz[F]: bin centres and quadrature weights of the integrals
+ *   over nu (P_KID and NEP^2 are sums of w_j * integrand_j).
+ * eta_z[n_pwv][F]: zenith transmission at PWV pwv0_mm + i*dpwv_mm; it is
+ *   interpolated linearly in optical depth -ln(eta_z) between rows, and
+ *   PWV outside the axis is clamped to it.  t_atm_K: physical temperature
+ *   of the atmosphere (stage 0).
+ * stages[n_stage]: the optics stages after the atmosphere, in order.
+ * Filters: K channels; f_hz, R, eta_peak [K] for LORENTZ / FILTERBANK, or
+ *   eta_filt[F][K] (row-major, channel fastest) for MATRIX.  Rows with
+ *   h nu < 2 Delta are zeroed (the KID gap cutoff).
+ * ref_pwv_mm, ref_el_rad: operating point of the reference spectrum; the
+ *   contraction is evaluated as (reference) + (deviation from it), which
+ *   is exact algebra and keeps FP32 accumulation error proportional to the
+ *   deviation.  The reference NEP^2 also sets the 1/f amplitude
+ *   (gtod_job.pink_knee_hz).
+ * All pointers are host memory.  Synchronous.
+ * Errors: EINVAL (F < 1, K < 1, n_pwv < 2, bad mode/kind, non-positive
+ * weights or dpwv), EBUDGET, ENOMEM, EDEVICE.
+ */
+typedef struct gtod_spectral_desc {
+  int32_t F;
+  int32_t K;
+  const double* nu_hz;
+  const double* w_hz;
+  int32_t n_pwv;
+  int32_t filter_mode;
+  double pwv0_mm, dpwv_mm;
+  const double* eta_z;
+  double t_atm_K;
+  int32_t n_stage;
+  int32_t reserved0;
+  const gtod_stage* stages;
+  const double* f_hz;
+  const double* R;
+  const double* eta_peak;
+  const double* eta_filt;
+  double ref_pwv_mm;
+  double ref_el_rad;
+} gtod_spectral_desc;
+
+gtod_status gtod_load_filters(gtod_ctx* ctx, const gtod_spectral_desc* desc,
+                              int32_t* id);
+
+/* job kinds */
+#define GTOD_JOB_SIGNAL 0   /* power, photon noise: rows [t_begin,t_end)  */
+#define GTOD_JOB_PINK 1     /* 1/f noise: all t_total samples             */
+/* scan kinds (section 2.4) */
+#define GTOD_SCAN_STARE 0   /* (phi, theta) = (0, 0)                      */
+#define GTOD_SCAN_DAISY 1   /* Eq. daisy: params {r_petal, omega, Omega}  */
+#define GTOD_SCAN_TRAJ 2    /* user pattern: device double traj[t_total][2]
+                               holding (phi, theta) per sample            */
+/* job flags */
+#define GTOD_JOB_PHOTON_NOISE 1u  /* add sigma*z (SIGNAL)                 */
+#define GTOD_JOB_ACCUMULATE 2u    /* add into tod instead of overwriting  */
+
+/*
+ * One unit of work for gtod_simulate_tod.
+ *
+ * Pixels: n_pix spaxels with pointing offsets dphi_rad/dtheta_rad (host
+ *   [n_pix]).  Pixel p of the job keys the noise counters.
+ * Scan: (phi(t), theta(t)) around the scan offset (phi0, theta0), t =
+ *   n / f_sample for absolute sample n.  Screen coordinates use
+ *   phi(t)+dphi, theta(t)+dtheta (Eq. xy_atm); the airmass and the source
+ *   use the full pointing phi(t)+phi0+dphi, theta(t)+theta0+dtheta.
+ * Source: pre-convolved P_nu,src cube (device float [n_el][n_az][cube_ld],
+ *   cube_ld >= F spectral stride), node (i_az, i_el) at (az0 + i_az*daz,
+ *   el0 + i_el*del); bilinear inside the closed grid, zero outside; NULL
+ *   for no source.
+ * Samples: SIGNAL computes rows t in [t_begin, t_end) of a t_total-long
+ *   observation; PINK computes all t_total samples of every (p, k) series.
+ * Noise: seed keys Philox4x32-10 with key (seed mod 2^32, seed >> 32);
+ *   white noise of sample (t, k, p) uses counter (t, k, p, 0), bin j of
+ *   the 1/f spectrum of series (p, k) uses counter (j, k, p, 1).
+ *   PINK: PSD A_k f^-alpha_k with A_k = NEP^2_ref,k * pink_knee_hz^alpha_k
+ *   (pink_alpha host [K]).
+ * Outputs (device, caller-owned; layout [n_pix][K][t_total], time fastest):
+ *   tod (required): power (+ noise) in W.  p_kid, sigma (optional, SIGNAL):
+ *   noise-free power and photon-noise sigma.  pwv (optional, SIGNAL):
+ *   [n_pix][t_total] zenith PWV sampled at each row.
+ */
+typedef struct gtod_job {
+  int32_t kind;
+  int32_t screen_id;
+  int32_t spec_id;
+  int32_t n_pix;
+  const double* dphi_rad;
+  const double* dtheta_rad;
+  int32_t scan_kind;
+  int32_t precision;          /* GTOD_PREC_* or -1 for the ctx default    */
+  double phi0_rad, theta0_rad;
+  double scan_params[8];
+  const double* traj;
+  const float* cube;
+  int32_t n_az, n_el;
+  int64_t cube_ld;
+  double az0_rad, daz_rad, el0_rad, del_rad;
+  int64_t t_begin, t_end, t_total;
+  uint64_t seed;
+  uint32_t flags;
+  int32_t reserved0;
+  const double* pink_alpha;
+  double pink_knee_hz;
+  float* tod;
+  float* p_kid;
+  float* sigma;
+  float* pwv;
+} gtod_job;
+
+/*
+ * gtod_simulate_tod -- enqueue n_jobs jobs on hip_stream (a hipStream_t;
+ * NULL for the legacy default stream) and return without waiting.
+ * All jobs are validated first; on any error nothing is enqueued.  Host
+ * arrays named by the jobs are consumed before return.  Each stream gets
+ * its own workspace on first use; calls on one stream run in order.
+ * Errors: EINVAL, ENOTFOUND, ERANGE (STRICT_RANGE), EBUDGET (first use of
+ * a stream), EDEVICE (outputs are undefined afterwards).
+ */
+gtod_status gtod_simulate_tod(gtod_ctx* ctx, const gtod_job* jobs,
+                              int32_t n_jobs, void* hip_stream);
+
+/* object kinds for gtod_free */
+#define GTOD_OBJ_SCREEN 0
+#define GTOD_OBJ_SPEC 1
+#define GTOD_OBJ_CTX 2
+/*
+ * gtod_free -- release a resident screen or spectral setup (after the
+ * device has finished all work queued so far), or the whole context
+ * (id ignored).  Returns the memory to the budget.
+ * Errors: ENOTFOUND for an unknown id, EINVAL for a bad kind.
+ */
+gtod_status gtod_free(gtod_ctx* ctx, int32_t kind, int32_t id);
+
+/* ---- utilities (not part of the simulation path) ---------------------- */
+
+/* Message for the last failed call on ctx (NULL ctx: last init failure). */
+const char* gtod_last_error(const gtod_ctx* ctx);
+
+/* Bytes currently charged to the budget, and the budget itself. */
+gtod_status gtod_memory(const gtod_ctx* ctx, uint64_t* used, uint64_t* budget);
+
+/* Range events since init: out[0] screen positions clamped to the edge,
+ * out[1] PWV values clamped to the table axis.  Synchronises the device. */
+gtod_status gtod_get_counters(gtod_ctx* ctx, uint64_t out[2]);
+
+/* Reference NEP^2 per channel (W^2/Hz) of a spectral setup: the photon-
+ * noise level of the reference spectrum.  out: host [K]. */
+gtod_status gtod_spec_nep2_ref(gtod_ctx* ctx, int32_t spec_id, double* out);
+
+/* Raw Philox4x32-10 words for n counters (device uint32 ctr[n][4] in,
+ * device uint32 out[n][4]) under key (seed mod 2^32, seed >> 32), on the
+ * given stream: the same generator the noise kernels use. */
+gtod_status gtod_philox(gtod_ctx* ctx, const uint32_t* ctr, uint32_t* out,
+                        int64_t n, uint64_t seed, void* hip_stream);
+
+/* sizeof of the descriptor structs, for binding checks (no device use):
+ * out[0..4] = init, screen, stage, spectral, job. */
+void gtod_abi_sizes(int64_t out[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GTOD_H */

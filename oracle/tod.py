@@ -39,15 +39,19 @@ def bilinear_clamped(grid, gx, gy):
 
 
 def lut_transmission(spec, pwv_mm):
-    """eta_atm,z(nu) at each PWV by linear interpolation in eta between the
-    table rows (section 2.4, the 2-D lookup table); PWV outside the table
-    axis is clamped to it.  Returns ([rows][F], clamped[rows])."""
+    """eta_atm,z(nu) at each PWV from the 2-D lookup table (section 2.4).
+
+    The paper does not say how the table is interpolated.  Reading: linear
+    in optical depth tau = -ln(eta_z) between the two bracketing PWV rows,
+    which is exact wherever the zenith opacity is linear in PWV; PWV outside
+    the table axis is clamped to it.  Table entries must lie in (0, 1].
+    Returns ([rows][F], clamped[rows])."""
     n = spec.eta_z.shape[0]
     g = (np.asarray(pwv_mm, np.float64) - spec.pwv0_mm) / spec.dpwv_mm
     i, w, clamped = _clamped_cell(g, n)
-    eta = ((1.0 - w)[:, None] * spec.eta_z[i, :]
-           + w[:, None] * spec.eta_z[i + 1, :])
-    return eta, clamped
+    tau = -np.log(spec.eta_z)
+    tz = (1.0 - w)[:, None] * tau[i, :] + w[:, None] * tau[i + 1, :]
+    return np.exp(-tz), clamped
 
 
 def source_power(src, az, el):

@@ -169,9 +169,10 @@ def test_source_zero_outside_grid_and_exact_at_nodes():
                                             + cube[8, 3]), rtol=1e-15)
 
 
-def test_lut_nodes_follow_exponential_law():
-    """At table nodes the interpolated transmission is the table row, so
-    eta_z^csc equals exp(-tau PWV csc) of the synthetic law."""
+def test_lut_follows_exponential_law_between_nodes():
+    """The synthetic table is eta_z = exp(-tau(nu) PWV); interpolation in
+    optical depth reproduces it at any PWV, and eta_z^csc equals
+    exp(-tau PWV csc)."""
     sc = tiny_scenario()
     sp = sc.spectral
     lines = gen.absorption_lines(3, lo_hz=300e9, hi_hz=340e9)
@@ -179,20 +180,20 @@ def test_lut_nodes_follow_exponential_law():
         a / (1 + ((sp.nu_hz - n) / g) ** 2)
         for n, g, a in zip(lines["nu_hz"], lines["gamma_hz"],
                            lines["a_per_mm"]))
-    pwv = sp.pwv0_mm + sp.dpwv_mm * np.array([0, 7, 20, 60])
+    pwv = np.array([0.0, 0.35, 0.987654, 1.5, 2.999])
     eta, cl = ot.lut_transmission(sp, pwv)
     assert not cl.any()
     csc = 1 / np.sin(np.pi / 3)
     np.testing.assert_allclose(eta ** csc, np.exp(-np.outer(pwv, tau) * csc),
                                rtol=1e-13)
-    # beyond the axis: clamped to the last row
+    # beyond the axis: clamped to the first / last row
     eta2, cl2 = ot.lut_transmission(sp, np.array([99.0, -1.0]))
     assert cl2.all()
-    np.testing.assert_array_equal(eta2[0], sp.eta_z[-1])
+    np.testing.assert_allclose(eta2[0], sp.eta_z[-1], rtol=1e-15)
     np.testing.assert_array_equal(eta2[1], sp.eta_z[0])
-    # linear in eta between rows: midpoint is the mean of the rows
+    # halfway between rows: geometric mean of the two rows
     mid, _ = ot.lut_transmission(sp, np.array([sp.pwv0_mm + 2.5 * sp.dpwv_mm]))
-    np.testing.assert_allclose(mid[0], 0.5 * (sp.eta_z[2] + sp.eta_z[3]),
+    np.testing.assert_allclose(mid[0], np.sqrt(sp.eta_z[2] * sp.eta_z[3]),
                                rtol=1e-14)
 
 
@@ -232,7 +233,7 @@ def test_p2_single_stage_closed_form():
         a / (1 + ((sp.nu_hz - n) / g) ** 2)
         for n, g, a in zip(lines["nu_hz"], lines["gamma_hz"],
                            lines["a_per_mm"]))
-    pwv = np.array([sp.dpwv_mm * 20])
+    pwv = np.array([sp.dpwv_mm * 20.37])
     csc = 1 / np.sin(np.pi / 3)
     eta_z, _ = ot.lut_transmission(sp, pwv)
     P = ot.cascade(sc, eta_z ** csc, None)[0]
@@ -407,7 +408,8 @@ def test_p11_brute_force_tiny(filt):
             wa, we = ga - ia, ge - ie
             for j in range(F):
                 nu = sp.nu_hz[j]
-                ez = (1 - wl) * sp.eta_z[il, j] + wl * sp.eta_z[il + 1, j]
+                ez = np.exp((1 - wl) * np.log(sp.eta_z[il, j])
+                            + wl * np.log(sp.eta_z[il + 1, j]))
                 ea = ez ** (1 / np.sin(el))
                 C = src.cube.astype(np.float64)
                 ps = ((1 - wa) * (1 - we) * C[ie, ia, j] + wa * (1 - we) * C[ie, ia + 1, j]
