@@ -1,0 +1,217 @@
+"""Throughput benchmark: detector-samples/s of the full simulation on one GPU.
+
+One step = one gtod_simulate_tod call covering the whole observation of the
+workload: the SIGNAL job (pointing, screen, table + airmass, cascade,
+filterbank contraction, photon noise) over every (pixel, sample) and the
+PINK job (1/f noise for every (pixel, channel) series, added in place).
+Inputs (screen, tables, filter matrices, source cube) are resident in HBM
+before the timed region; outputs stay in HBM.
+
+Prints one JSON line.  See `python bench.py --help`.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("detector-samples/s (t×pix×chan) at ≤1e-6 rel err vs "
+          "FP64; p50/p99 request ms")
+PEAK = {"fp32": 157.3e12, "split": 2.5e15}   # dense MFMA FLOP/s (MI355X)
+HBM_PEAK = 8.0e12
+
+WORKLOADS = {
+    "c2": "single-pixel spectrometer: 1 px raster +-60\" at 0.5 deg/s, "
+          "347-channel filterbank R=500 220-440 GHz, 3000 bins, 600 s at "
+          "160 Hz (96000 samples), 512x65536 PWV screen, 6-stage cascade, "
+          "Gaussian source with 350 GHz line, photon + 1/f noise",
+    "c3": "IFU: 7x7 = 49 px at 12\" pitch, daisy r=90\", 347-channel "
+          "filterbank R=500 220-440 GHz, 3000 bins, 1 h at 160 Hz (576000 "
+          "samples), 1024x262144 PWV screen, 6-stage cascade, Gaussian "
+          "source with 350 GHz line, photon + 1/f noise (knee 1 Hz, alpha 1)",
+    "c4": "IFU as c3 plus a faint 60\" Gaussian source (1e-4 of the "
+          "loading), split hi+lo BF16 contraction",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=["fp32", "split"])
+    ap.add_argument("--workspace-gib", type=float, default=8.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def scenario(name):
+    from workloads import configs
+    return {"c2": configs.c2, "c3": configs.c3, "c4": configs.c4}[name]()
+
+
+def cpu_baseline(sc, target_s):
+    """The FP64 oracle, as it is, on a bounded sample of the same workload:
+    all pixels over a window of samples in the middle of the observation,
+    plus two full 1/f series; scaled to detector-samples/s."""
+    import numpy as np
+    import oracle
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()]
+                      or [1])
+    except Exception:  # pragma: no cover
+        threads = os.cpu_count() or 1
+    mid = sc.t_total // 2
+    t0 = time.perf_counter()
+    oracle.tod.simulate(sc, mid, mid + 8)
+    probe = time.perf_counter() - t0
+    n = int(max(8, min(sc.t_total - mid, (target_s * 0.8) / probe * 8)))
+    t0 = time.perf_counter()
+    oracle.tod.simulate(sc, mid, mid + n)
+    t_sig = time.perf_counter() - t0
+    nep2 = oracle.tod.reference_nep2(sc)
+    A = oracle.pink.amplitude(nep2, sc.pink_alpha, sc.pink_knee_hz)
+    t0 = time.perf_counter()
+    for k in (0, sc.K - 1):
+        oracle.pink.series(sc.seed, 0, k, A[k], sc.pink_alpha[k], sc.t_total,
+                           sc.f_sample_hz)
+    t_pink_series = (time.perf_counter() - t0) / 2
+    det = sc.n_pix * sc.K * n
+    per_det = t_sig / det + t_pink_series / sc.t_total
+    return {"value": 1.0 / per_det, "unit": "detector-samples/s",
+            "cores": int(threads), "kind": "oracle",
+            "sample": (f"{sc.n_pix} px x {sc.K} ch x {n} samples of the "
+                       f"signal path ({t_sig:.1f} s) plus two full "
+                       f"{sc.t_total}-sample 1/f series "
+                       f"({t_pink_series:.2f} s each), combined per "
+                       f"detector-sample")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU; --gpus {args.gpus} is not "
+              "supported (the simulation shards by pixel or request with no "
+              "exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2604_23305_amd as g
+
+    prec_name = args.precision or ("split" if args.workload == "c4" else "fp32")
+    prec = g.PREC_SPLIT_BF16 if prec_name == "split" else g.PREC_FP32
+    t_setup = time.perf_counter()
+    sc = scenario(args.workload)
+    ctx = g.sim_init(device=0, precision=prec,
+                     workspace_bytes=int(args.workspace_gib * (1 << 30)))
+    run = g.ScenarioRun(ctx, sc)
+    out = run.alloc()
+    jobs = [run.signal_job(out), run.pink_job(out.tod, accumulate=True)]
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t_setup
+    print(f"# setup {setup_s:.1f} s; workload {args.workload} ({prec_name})",
+          file=sys.stderr, flush=True)
+
+    for w in range(args.warmup):
+        g.simulate_tod(ctx, jobs, stream)
+        torch.cuda.synchronize()
+        print(f"# warmup {w} done", file=sys.stderr, flush=True)
+
+    g.profile_enable(ctx, True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for s in range(args.steps):
+        g.simulate_tod(ctx, jobs, stream)
+        ev[s + 1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = g.profile_read(ctx)
+    g.profile_enable(ctx, False)
+    step_ms = [ev[s].elapsed_time(ev[s + 1]) for s in range(args.steps)]
+    det_per_step = sc.n_pix * sc.K * sc.t_total
+    value = det_per_step * args.steps / elapsed
+    print(f"# timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr,
+          flush=True)
+
+    F, K = sc.F, sc.K
+    kern = {}
+    for name, (ms, n, units) in prof.items():
+        if n == 0:
+            continue
+        d = {"launches": n, "avg_ms": ms / n, "total_ms": ms}
+        sec = ms / 1e3
+        if name.startswith("gemm"):
+            d["alg_tflops"] = 6.0 * K * F * units / sec / 1e12
+        elif name == "panel":
+            # per row: 4 source spectra (16F B), the deviation row (4F B),
+            # 4 screen values (32 B)
+            d["alg_gbs"] = (20.0 * F + 32.0) * units / sec / 1e9
+        else:
+            # per complex point: one 8-byte write (pass 1) or read (pass 2)
+            # plus, in pass 2, the in-place add into the TOD (8 B / point)
+            per = 8.0 if name == "pink_pass1" else 16.0
+            d["alg_gbs"] = per * units / sec / 1e9
+        kern[name] = d
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    dd = kern[dom]
+    if dom.startswith("gemm"):
+        achieved = dd["alg_tflops"]
+        peak = PEAK["split" if dom.endswith("bf16") else "fp32"] / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s"}
+    else:
+        achieved = dd["alg_gbs"]
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s"}
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["kernel"] = dom
+    roof["traffic"] = None
+    tf = os.path.join(ROOT, "profiles", f"traffic_{dom}_{args.workload}.json")
+    if os.path.exists(tf):
+        roof["traffic"] = json.load(open(tf)).get("bytes_per_launch")
+
+    res = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "detector-samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec_name == "fp32" else "bf16x2",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
+                   "pixels": sc.n_pix, "channels": K, "freq_bins": F,
+                   "samples": sc.t_total, "precision": prec_name,
+                   "parallelism": "single GPU"},
+        "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
+                       "p99": float(np.percentile(step_ms, 99))},
+        "roofline": roof,
+        "kernels": kern,
+    }
+    g.free(ctx)
+    del out
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

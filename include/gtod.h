@@ -305,6 +305,22 @@ gtod_status gtod_spec_nep2_ref(gtod_ctx* ctx, int32_t spec_id, double* out);
 gtod_status gtod_philox(gtod_ctx* ctx, const uint32_t* ctr, uint32_t* out,
                         int64_t n, uint64_t seed, void* hip_stream);
 
+/* Per-kernel timing.  While enabled, every kernel launch is bracketed by
+ * HIP events recorded on its launch stream.  gtod_profile_enable(ctx, 1)
+ * clears the totals and starts; 0 stops.  gtod_profile_read synchronises
+ * the device and writes, for each kernel id k < n_kernels,
+ * out[3k] = total milliseconds, out[3k+1] = launches, out[3k+2] = work
+ * units (rows for the panel and contraction kernels, complex points for
+ * the two 1/f passes). */
+#define GTOD_KERNEL_PANEL 0
+#define GTOD_KERNEL_GEMM_F32 1
+#define GTOD_KERNEL_GEMM_BF16 2
+#define GTOD_KERNEL_PINK1 3
+#define GTOD_KERNEL_PINK2 4
+#define GTOD_N_KERNELS 5
+gtod_status gtod_profile_enable(gtod_ctx* ctx, int32_t enable);
+gtod_status gtod_profile_read(gtod_ctx* ctx, double* out, int32_t n_kernels);
+
 /* sizeof of the descriptor structs, for binding checks (no device use):
  * out[0..4] = init, screen, stage, spectral, job. */
 void gtod_abi_sizes(int64_t out[5]);

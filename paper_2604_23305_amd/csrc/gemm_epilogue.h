@@ -1,0 +1,74 @@
+// Epilogue shared by the contraction kernels: reference terms, photon-noise
+// sigma, Philox white noise and the store into [pixel][channel][time].
+//
+// Each wave owns 2 x 2 accumulator tiles of 32 channels x 32 samples (3
+// products).  A tile is first written to the wave's slice of LDS with
+// static register indices, then read back by a compact loop in which lane
+// l handles sample (l mod 32) of channel rows 2s + l/32: stores are runs of
+// 32 consecutive samples.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "gtod_internal.h"
+#include "philox.h"
+
+namespace gtod {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kEpiPitch = 33;
+constexpr int kEpiWaveFloats = 2 * 32 * kEpiPitch;
+
+__device__ __forceinline__ void contraction_epilogue(
+    const GemmArgs& a, f32x16 (&acc)[3][2][2], float* smem, int64_t row0,
+    int ch0, int wt, int wc, const bool (&live)[2]) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int h = lane >> 5, c = lane & 31;
+  float* spk = smem + wave * kEpiWaveFloats;
+  float* sn2 = spk + 32 * kEpiPitch;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      __syncthreads();
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int chl = 8 * (e >> 2) + 4 * h + (e & 3);
+        spk[chl * kEpiPitch + c] = acc[0][i][j][e];
+        sn2[chl * kEpiPitch + c] = acc[1][i][j][e] + acc[2][i][j][e];
+      }
+      __syncthreads();
+      if (!live[i]) continue;
+      const int64_t row = row0 + wt * 64 + j * 32 + c;
+      const int pl = (int)(row / a.Tpad);
+      const int tl = (int)(row % a.Tpad);
+      if (pl >= a.n_pix || tl >= a.Tc) continue;
+      const int p = a.p0 + pl;
+      const int64_t t = a.t0 + tl;
+      const int chb = ch0 + wc * 64 + i * 32;
+      for (int s = 0; s < 16; ++s) {
+        const int chl = 2 * s + h;
+        const int ch = chb + chl;
+        if (ch >= a.K) break;
+        const float pk = (float)a.c0[ch] + spk[chl * kEpiPitch + c];
+        const float n2 = (float)a.c1[ch] + sn2[chl * kEpiPitch + c];
+        const float sg = sqrtf(fmaxf(n2, 0.f) * a.fs_half);
+        float v = pk;
+        if (a.photon) {
+          const u32x4 o = philox10(u32x4{(uint32_t)t, (uint32_t)ch, (uint32_t)p, 0u},
+                                   a.key0, a.key1);
+          float zc, zs;
+          box_muller(o.x, o.y, &zc, &zs);
+          v += sg * zc;
+        }
+        const int64_t off = ((int64_t)p * a.K + ch) * a.t_total + t;
+        if (a.accumulate) a.tod[off] += v; else a.tod[off] = v;
+        if (a.p_kid) a.p_kid[off] = pk;
+        if (a.sigma) a.sigma[off] = sg;
+      }
+    }
+  }
+}
+
+}  // namespace gtod

@@ -1,0 +1,137 @@
+// Internal types and kernel launchers of the gtod library (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gtod {
+
+// Frequency axis padded to a multiple of the contraction depth chunk, the
+// channel axis to a multiple of the 32-wide MFMA tile.
+constexpr int kFPad = 32;
+constexpr int kKPad = 32;
+// Rows of one contraction tile (time samples of one pixel) and of one
+// panel block.  A pixel's rows inside a chunk are padded to kRowPad.
+constexpr int kRowPad = 128;
+constexpr int kPanelRows = 32;
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+// Everything the panel kernel needs for one chunk of rows.
+// Rows of the chunk: r = pl * Tpad + tl for local pixel pl in [0, n_pix)
+// and local sample tl in [0, Tpad); a row is valid when tl < Tc; its
+// absolute sample is t0 + tl and its job pixel is p0 + pl.
+struct PanelArgs {
+  const float* tau;      // [n_pwv][Fp] zenith optical depth
+  const float* E;        // [Fp] emission with a transparent sky
+  const float* D;        // [Fp] coefficient of the sky emissivity
+  const float* W;        // [Fp] gain on the source
+  const float* Pref;     // [Fp] reference spectrum
+  int F, Fp, n_pwv;
+  double pwv0, dpwv;
+  const double* scr;     // [ny][nx]
+  int64_t nx, ny;
+  double dx, dy, ix0, iy0, h, wind;
+  int scan_kind;
+  double phi0, theta0, r_petal, omega, Omega;
+  const double* traj;    // [t_total][2]
+  double f_s;
+  const double* dphi;    // [n_pix_job] device
+  const double* dtheta;
+  int p0, n_pix;
+  const float* cube;     // [n_el][n_az][cube_ld] or null
+  int n_az, n_el;
+  int64_t cube_ld;
+  double az0, daz, el0, del;
+  int64_t t0;
+  int Tc, Tpad;
+  float* panel;          // [n_pix*Tpad][Fp]
+  float* pwv_out;        // [n_pix_job][t_total] or null
+  int64_t t_total;
+  unsigned long long* counters;  // [2]
+};
+
+struct GemmArgs {
+  const float* panel;    // [rows][Fp] deviations dP
+  const float* B;        // [3][Kp][Fp] B0, B1', B2 (fp32)
+  const uint16_t* Bh;    // [3][Kp][Fp] bf16 hi
+  const uint16_t* Bl;    // [3][Kp][Fp] bf16 lo
+  const double* c0;      // [Kp] reference P_KID
+  const double* c1;      // [Kp] reference NEP^2
+  int Fp, K, Kp;
+  int p0, n_pix, Tc, Tpad;
+  int64_t t0, t_total;
+  float fs_half;
+  uint32_t key0, key1;
+  int photon, accumulate;
+  float* tod;
+  float* p_kid;
+  float* sigma;
+  int n_tt, n_cg;
+};
+
+struct PinkArgs {
+  int64_t s0;            // first series of the batch (series = p*K + k)
+  int n_series;
+  int K;
+  int M, M1, M2, lgM1, lgM2, N;
+  double fs;
+  float2* scratch;       // [n_series][M1][M2]
+  const float* scale;    // [K] sqrt(A_k N fs / 4) / N
+  const float* alpha;    // [K]
+  uint32_t key0, key1;
+  float* tod;
+  int64_t t_total;
+  int accumulate;
+  int B2;
+};
+
+// setup kernels (FP64)
+struct SpecSetupArgs {
+  int F, Fp, K, Kp, n_pwv, n_pass, mode;
+  const double* nu;      // [F]
+  const double* w;       // [F]
+  const double* eta_z;   // [n_pwv][F]
+  const double* pass_eta;   // [n_pass][F]
+  const int* pass_kind;     // [n_pass]: 0 fixed temperature, 1 sky
+  const double* pass_T;     // [n_pass]
+  const double* f_hz; const double* R; const double* eta_peak;  // [K]
+  const int* order;         // [K] upstream order (filterbank)
+  const double* eta_filt;   // [F][K] (matrix mode)
+  double t_atm, t_cmb, eta_taper, rho_surf, eta_pol, delta_J, eta_pb;
+  double ref_pwv, pwv0, dpwv, ref_el;
+  // outputs
+  float* tau; float* E; float* D; float* W; float* Pref;
+  double* Pref64;           // [Fp] the FP32 reference widened (exact)
+  double* B64;              // [3][F][K] scratch (B0, B1, B2)
+  float* B;                 // [3][Kp][Fp]
+  uint16_t* Bh; uint16_t* Bl;
+  double* c0; double* c1;   // [Kp]
+};
+
+// Optics passes after the atmosphere.  type: 0 eta from pool[off + j],
+// 1 constant prm[0], 2 Ohmic (eps_ref, nu_ref), 3 dielectric absorption
+// (d, n, tan delta), 4 dielectric surface (n).  coupling: 0 to P_JN(T),
+// 1 to the sky.
+struct PassTable {
+  int n;
+  const int* type;
+  const int* coupling;
+  const int* off;
+  const double* prm;   // [n][3]
+  const double* T;
+  const double* pool;
+};
+
+void launch_spec_setup(const SpecSetupArgs& a, const PassTable& pt,
+                       hipStream_t s);
+void launch_panel(const PanelArgs& a, hipStream_t s);
+void launch_gemm_f32(const GemmArgs& a, hipStream_t s);
+void launch_gemm_bf16(const GemmArgs& a, hipStream_t s);
+void launch_pink_pass1(const PinkArgs& a, hipStream_t s);
+void launch_pink_pass2(const PinkArgs& a, hipStream_t s);
+void launch_philox(const uint32_t* ctr, uint32_t* out, int64_t n,
+                   uint32_t k0, uint32_t k1, hipStream_t s);
+
+}  // namespace gtod

@@ -1,0 +1,176 @@
+// Filterbank contraction with split BF16 operands on the matrix cores
+// (v_mfma_f32_32x32x16_bf16, FP32 accumulation), same epilogue as the FP32
+// kernel.
+//
+// Every FP32 operand x is carried as x_hi + x_lo with x_hi = bf16(x) and
+// x_lo = bf16(x - x_hi) (round to nearest even), which keeps about 16
+// significant bits.  Per tile pair the kernel accumulates
+//   C0 = B0lo dPhi + B0hi dPlo + B0hi dPhi
+//   C1 = B1lo dPhi + B1hi dPlo + B1hi dPhi
+//   C2 = B2hi (dP^2)hi
+// (the lo x lo products and the low half of the small dP^2 term are below
+// the FP32 rounding of the result).  The deviations dP are a few percent
+// of P, so the 16-bit operands give about 1e-7 relative error on P_KID.
+// dP is split once, when a chunk is staged into LDS; the response halves
+// come pre-split from the spectral setup.
+#include <hip/hip_runtime.h>
+
+#include "gtod_internal.h"
+#include "gemm_epilogue.h"
+#include "philox.h"
+
+namespace gtod {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+
+constexpr int MT = 128;
+constexpr int NT = 128;
+constexpr int KC = 32;        // bins per chunk = 2 MFMA steps of 16
+constexpr int LPB = KC + 8;   // padded LDS row in bf16 (80 bytes)
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
+  const int b = blockIdx.x;
+  const int xcd = b & 7;
+  const int l = b >> 3;
+  const int tt = (l / a.n_cg) * 8 + xcd;
+  const int cg = l % a.n_cg;
+  if (tt >= a.n_tt) return;
+  const int64_t row0 = (int64_t)tt * MT;
+  const int ch0 = cg * NT;
+
+  // sD: [3][MT][LPB] dP hi, dP lo, (dP^2) hi; sB: [5][NT][LPB] B0h B0l B1h B1l B2h
+  __shared__ float smem[(3 * MT * LPB + 5 * NT * LPB) / 2];
+  static_assert((3 * MT * LPB + 5 * NT * LPB) / 2 >= 4 * kEpiWaveFloats, "epilogue LDS");
+  __bf16* sD = reinterpret_cast<__bf16*>(smem);
+  __bf16* sB = sD + 3 * MT * LPB;
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wt = wave & 1, wc = wave >> 1;
+  const int h = lane >> 5, c = lane & 31;
+
+  f32x16 acc[3][2][2];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[m][i][j][e] = 0.f;
+
+  const int64_t Fp = a.Fp;
+  const int64_t KF = (int64_t)a.Kp * Fp;
+  // panel chunk: 128 rows x 32 floats = 1024 float4, 4 per thread
+  // response chunk: 5 x 128 x 32 bf16 = 2560 x 16 bytes, 10 per thread
+  float4 rd[4];
+  uint4 rb[10];
+  auto load_chunk = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + q * 256;
+      const int row = idx >> 3, c4 = idx & 7;
+      rd[q] = *reinterpret_cast<const float4*>(a.panel + (row0 + row) * Fp + k0 + 4 * c4);
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const int idx = tid + q * 256;
+      const int mm = idx >> 9, rem = idx & 511;
+      const int ch = rem >> 2, c8 = rem & 3;
+      const int gch = ch0 + ch;
+      // mm: 0 B0h, 1 B0l, 2 B1h, 3 B1l, 4 B2h
+      const uint16_t* base = (mm & 1) ? a.Bl : a.Bh;
+      const int m = mm >> 1;
+      if (gch < a.Kp)
+        rb[q] = *reinterpret_cast<const uint4*>(base + m * KF + (int64_t)gch * Fp + k0 + 8 * c8);
+      else
+        rb[q] = make_uint4(0u, 0u, 0u, 0u);
+    }
+  };
+  auto store_chunk = [&]() {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + q * 256;
+      const int row = idx >> 3, c4 = idx & 7;
+      const float x[4] = {rd[q].x, rd[q].y, rd[q].z, rd[q].w};
+      bf16x4 hi, lo, sq;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        hi[e] = (__bf16)x[e];
+        lo[e] = (__bf16)(x[e] - (float)hi[e]);
+        sq[e] = (__bf16)(x[e] * x[e]);
+      }
+      const int o = row * LPB + 4 * c4;
+      *reinterpret_cast<bf16x4*>(&sD[o]) = hi;
+      *reinterpret_cast<bf16x4*>(&sD[MT * LPB + o]) = lo;
+      *reinterpret_cast<bf16x4*>(&sD[2 * MT * LPB + o]) = sq;
+    }
+#pragma unroll
+    for (int q = 0; q < 10; ++q) {
+      const int idx = tid + q * 256;
+      const int mm = idx >> 9, rem = idx & 511;
+      const int ch = rem >> 2, c8 = rem & 3;
+      *reinterpret_cast<uint4*>(&sB[(mm * NT + ch) * LPB + 8 * c8]) = rb[q];
+    }
+  };
+
+  bool live[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) live[i] = (ch0 + wc * 64 + i * 32) < a.K;
+
+  load_chunk(0);
+  for (int k0 = 0; k0 < a.Fp; k0 += KC) {
+    __syncthreads();
+    store_chunk();
+    __syncthreads();
+    if (k0 + KC < a.Fp) load_chunk(k0 + KC);
+#pragma unroll
+    for (int s = 0; s < KC / 16; ++s) {
+      const int col = 16 * s + 8 * h;
+      bf16x8 dh[2], dl[2], ds[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int o = (wt * 64 + j * 32 + c) * LPB + col;
+        dh[j] = *reinterpret_cast<const bf16x8*>(&sD[o]);
+        dl[j] = *reinterpret_cast<const bf16x8*>(&sD[MT * LPB + o]);
+        ds[j] = *reinterpret_cast<const bf16x8*>(&sD[2 * MT * LPB + o]);
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (live[i]) {
+        const int ob = (wc * 64 + i * 32 + c) * LPB + col;
+        const bf16x8 b0h = *reinterpret_cast<const bf16x8*>(&sB[0 * NT * LPB + ob]);
+        const bf16x8 b0l = *reinterpret_cast<const bf16x8*>(&sB[1 * NT * LPB + ob]);
+        const bf16x8 b1h = *reinterpret_cast<const bf16x8*>(&sB[2 * NT * LPB + ob]);
+        const bf16x8 b1l = *reinterpret_cast<const bf16x8*>(&sB[3 * NT * LPB + ob]);
+        const bf16x8 b2h = *reinterpret_cast<const bf16x8*>(&sB[4 * NT * LPB + ob]);
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0l, dh[j], acc[0][i][j], 0, 0, 0);
+          acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0h, dl[j], acc[0][i][j], 0, 0, 0);
+          acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0h, dh[j], acc[0][i][j], 0, 0, 0);
+          acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1l, dh[j], acc[1][i][j], 0, 0, 0);
+          acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1h, dl[j], acc[1][i][j], 0, 0, 0);
+          acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1h, dh[j], acc[1][i][j], 0, 0, 0);
+          acc[2][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b2h, ds[j], acc[2][i][j], 0, 0, 0);
+        }
+        }
+      }
+    }
+  }
+
+  contraction_epilogue(a, acc, smem, row0, ch0, wt, wc, live);
+}
+
+void launch_gemm_bf16(const GemmArgs& a, hipStream_t s) {
+  const int64_t n_tt8 = round_up(a.n_tt, 8);
+  const int64_t blocks = n_tt8 * a.n_cg;
+  hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)blocks), dim3(256), 0, s, a);
+}
+
+}  // namespace gtod

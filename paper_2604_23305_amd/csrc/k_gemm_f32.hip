@@ -1,0 +1,169 @@
+// Filterbank contraction on the FP32 matrix cores, with the photon-noise
+// epilogue (sections 2.5-2.7).
+//
+// For a tile of 128 rows (consecutive samples of one pixel) x 128 channels
+// the kernel accumulates, over the frequency axis,
+//   C0 = dP B0,   C1 = dP B1',   C2 = dP^2 B2
+// with v_mfma_f32_32x32x2_f32.  The MFMA "A" operand is the channel-major
+// response (rows = channels) and "B" the deviation panel transposed, so the
+// 32x32 accumulator of a lane holds one time sample and 16 channels: the
+// epilogue stores runs of 32 consecutive samples per channel, matching the
+// [pixel][channel][time] output layout.
+// Epilogue: P_KID = c0 + C0, NEP^2 = c1 + C1 + C2, sigma = sqrt(NEP^2 f/2),
+// P_wn = sigma z with z from Philox counter (t, k, p, 0).
+//
+// Workgroup: 4 waves as 2 (time) x 2 (channel), each 64 x 64 = 2 x 2 MFMA
+// tiles per product.  Operands are staged through LDS in depth chunks of
+// 16 frequency bins; inside a chunk lane l takes bins 8*(l/32) .. +8, read
+// as 16-byte vectors.  Tile index -> workgroup mapping keeps the channel
+// groups of one time tile on the same XCD so the panel tile is fetched once
+// into that XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include "gtod_internal.h"
+#include "gemm_epilogue.h"
+#include "philox.h"
+
+namespace gtod {
+
+namespace {
+
+constexpr int MT = 128;   // rows per tile
+constexpr int NT = 128;   // channels per tile
+constexpr int KC = 16;    // frequency bins per LDS chunk
+constexpr int LP = KC + 4;  // padded LDS row (floats)
+
+}  // namespace
+
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
+  const int b = blockIdx.x;
+  const int xcd = b & 7;
+  const int l = b >> 3;
+  const int tt = (l / a.n_cg) * 8 + xcd;
+  const int cg = l % a.n_cg;
+  if (tt >= a.n_tt) return;
+  const int64_t row0 = (int64_t)tt * MT;
+  const int ch0 = cg * NT;
+
+  __shared__ float smem[MT * LP + 3 * NT * LP];
+  static_assert(MT * LP + 3 * NT * LP >= 4 * kEpiWaveFloats, "epilogue LDS");
+  float* sD = smem;
+  float* sB = smem + MT * LP;
+
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int wt = wave & 1, wc = wave >> 1;
+  const int h = lane >> 5, c = lane & 31;
+
+  f32x16 acc[3][2][2];
+#pragma unroll
+  for (int m = 0; m < 3; ++m)
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[m][i][j][e] = 0.f;
+
+  // global -> register staging: panel chunk 128 rows x 16 bins = 512 float4
+  // (2 per thread); response chunk 3 x 128 x 16 = 1536 float4 (6 per thread)
+  const int64_t Fp = a.Fp;
+  const int64_t KF = (int64_t)a.Kp * Fp;
+  float4 rd0, rd1, rb0, rb1, rb2, rb3, rb4, rb5;
+#define GTOD_LD_D(q, dst)                                                    \
+  {                                                                          \
+    const int idx = tid + (q) * 256;                                         \
+    dst = *reinterpret_cast<const float4*>(a.panel + (row0 + (idx >> 2)) * Fp + \
+                                           k0n + 4 * (idx & 3));             \
+  }
+#define GTOD_LD_B(q, dst)                                                    \
+  {                                                                          \
+    const int idx = tid + (q) * 256;                                         \
+    const int m = idx >> 9, rem = idx & 511;                                 \
+    const int gch = ch0 + (rem >> 2);                                        \
+    dst = gch < a.Kp ? *reinterpret_cast<const float4*>(                     \
+                           a.B + m * KF + (int64_t)gch * Fp + k0n + 4 * (rem & 3)) \
+                     : make_float4(0.f, 0.f, 0.f, 0.f);                      \
+  }
+#define GTOD_ST_D(q, src)                                                    \
+  {                                                                          \
+    const int idx = tid + (q) * 256;                                         \
+    *reinterpret_cast<float4*>(&sD[(idx >> 2) * LP + 4 * (idx & 3)]) = src;  \
+  }
+#define GTOD_ST_B(q, src)                                                    \
+  {                                                                          \
+    const int idx = tid + (q) * 256;                                         \
+    const int m = idx >> 9, rem = idx & 511;                                 \
+    *reinterpret_cast<float4*>(&sB[(m * NT + (rem >> 2)) * LP + 4 * (rem & 3)]) = src; \
+  }
+#define GTOD_LOAD_CHUNK                                                      \
+  GTOD_LD_D(0, rd0) GTOD_LD_D(1, rd1) GTOD_LD_B(0, rb0) GTOD_LD_B(1, rb1)   \
+  GTOD_LD_B(2, rb2) GTOD_LD_B(3, rb3) GTOD_LD_B(4, rb4) GTOD_LD_B(5, rb5)
+#define GTOD_STORE_CHUNK                                                     \
+  GTOD_ST_D(0, rd0) GTOD_ST_D(1, rd1) GTOD_ST_B(0, rb0) GTOD_ST_B(1, rb1)   \
+  GTOD_ST_B(2, rb2) GTOD_ST_B(3, rb3) GTOD_ST_B(4, rb4) GTOD_ST_B(5, rb5)
+
+  // channel tiles this wave owns that hold at least one real channel
+  bool live[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) live[i] = (ch0 + wc * 64 + i * 32) < a.K;
+
+  {
+    const int k0n = 0;
+    GTOD_LOAD_CHUNK
+  }
+  for (int k0 = 0; k0 < a.Fp; k0 += KC) {
+    __syncthreads();
+    GTOD_STORE_CHUNK
+    __syncthreads();
+    if (k0 + KC < a.Fp) {
+      const int k0n = k0 + KC;
+      GTOD_LOAD_CHUNK
+    }
+
+    // two half-steps of 4 bins: lane takes bins 8*h + 4*hs + (0..3)
+#pragma unroll
+    for (int hs = 0; hs < 2; ++hs) {
+      float4 dv[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+        dv[j] = *reinterpret_cast<const float4*>(&sD[(wt * 64 + j * 32 + c) * LP + 8 * h + 4 * hs]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (live[i]) {
+          float4 bv[3];
+#pragma unroll
+          for (int m = 0; m < 3; ++m)
+            bv[m] = *reinterpret_cast<const float4*>(
+                &sB[(m * NT + wc * 64 + i * 32 + c) * LP + 8 * h + 4 * hs]);
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              const float d = dv[j][s4];
+              acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[0][s4], d, acc[0][i][j], 0, 0, 0);
+              acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[1][s4], d, acc[1][i][j], 0, 0, 0);
+              acc[2][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[2][s4], d * d, acc[2][i][j], 0, 0, 0);
+            }
+          }
+        }
+      }
+    }
+  }
+
+  contraction_epilogue(a, acc, smem, row0, ch0, wt, wc, live);
+}
+#undef GTOD_LD_D
+#undef GTOD_LD_B
+#undef GTOD_ST_D
+#undef GTOD_ST_B
+#undef GTOD_LOAD_CHUNK
+#undef GTOD_STORE_CHUNK
+
+void launch_gemm_f32(const GemmArgs& a, hipStream_t s) {
+  const int64_t n_tt8 = round_up(a.n_tt, 8);
+  const int64_t blocks = n_tt8 * a.n_cg;
+  hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)blocks), dim3(256), 0, s, a);
+}
+
+}  // namespace gtod

@@ -1,0 +1,206 @@
+// Spectral setup kernels (FP64), run once per gtod_load_filters.
+//
+// Cascade collapse.  Every pass of Eq. radtrans is affine in the incoming
+// power, and the sky enters only through eta_atm, so the spectrum after the
+// last stage can be written exactly as
+//   P = E(nu) + xi_atm D(nu) + eta_atm W(nu) P_src,   xi_atm = 1 - eta_atm.
+// Starting from stage 0 (the atmosphere, section 2.5):
+//   E = P_JN(T_CMB), D = P_JN(T_atm) - P_JN(T_CMB), W = eta_t eta_surf eta_pol
+// and each later pass with efficiency eta maps
+//   fixed temperature T:  E <- eta E + (1-eta) P_JN(T), D <- eta D, W <- eta W
+//   sky-coupled:          E <- eta E + (1-eta) P_JN(T_CMB),
+//                         D <- eta D + (1-eta)(P_JN(T_atm) - P_JN(T_CMB)),
+//                         W <- eta W.
+// E, D and W are sums of non-negative terms, so evaluating P in FP32 has
+// only relative rounding error (no cancellation even when eta_atm ~ 1).
+//
+// Contraction tables (sections 2.5-2.6): with B0 = w eta, B1 = 2 w eta
+// (h nu + 2 Delta / eta_pb), B2 = 2 w eta^2,
+//   P_KID = P B0,  NEP^2 = P B1 + P^2 B2.
+// Writing P = Pref + dP (Pref the reference spectrum):
+//   P_KID = Pref B0 + dP B0
+//   NEP^2 = (Pref B1 + Pref^2 B2) + dP (B1 + 2 Pref B2) + dP^2 B2,
+// the constant parts c0, c1 are summed here in FP64 and the GEMM only
+// contracts the small deviations.
+#include <hip/hip_runtime.h>
+
+#include "gtod_internal.h"
+
+namespace gtod {
+
+namespace {
+
+constexpr double kH = 6.62607015e-34;
+constexpr double kKB = 1.380649e-23;
+constexpr double kC = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+
+__device__ double jn_power(double nu, double T) {
+  if (T <= 0.0) return 0.0;
+  return kH * nu / expm1(kH * nu / (kKB * T));
+}
+
+__device__ uint16_t bf16_rne(float x) {
+  uint32_t b = __float_as_uint(x);
+  b += 0x7FFFu + ((b >> 16) & 1u);
+  return (uint16_t)(b >> 16);
+}
+
+__device__ float bf16_to_f(uint16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+
+// Pass efficiency types, see gtod_runtime: 0 array, 1 constant, 2 Ohmic,
+// 3 dielectric absorption, 4 dielectric surface.
+__device__ double pass_eta(int type, const double* pool, int off, double p0,
+                           double p1, double p2, double nu, int j) {
+  switch (type) {
+    case 0: return pool[off + j];
+    case 1: return p0;
+    case 2: return 1.0 - p0 * sqrt(nu / p1);
+    case 3: return exp(-2.0 * kPi * p0 * p1 * p2 * nu / kC);
+    default: {
+      const double r = (1.0 - p0) / (1.0 + p0);
+      return 1.0 - r * r;
+    }
+  }
+}
+
+}  // namespace
+
+__global__ void k_spectral(SpecSetupArgs a, PassTable pt) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.Fp) return;
+  if (j >= a.F) {
+    a.E[j] = 0.f;
+    a.D[j] = 0.f;
+    a.W[j] = 0.f;
+    a.Pref[j] = 0.f;
+    a.Pref64[j] = 0.0;
+    for (int i = 0; i < a.n_pwv; ++i) a.tau[(int64_t)i * a.Fp + j] = 0.f;
+    return;
+  }
+  const double nu = a.nu[j];
+  const double bcmb = jn_power(nu, a.t_cmb);
+  const double batm = jn_power(nu, a.t_atm);
+  const double lam = kC / nu;
+  const double ruze = exp(-(4.0 * kPi * a.rho_surf / lam) *
+                          (4.0 * kPi * a.rho_surf / lam));
+  double E = bcmb, D = batm - bcmb, W = a.eta_taper * ruze * a.eta_pol;
+  for (int q = 0; q < pt.n; ++q) {
+    const double e = pass_eta(pt.type[q], pt.pool, pt.off[q], pt.prm[3 * q],
+                              pt.prm[3 * q + 1], pt.prm[3 * q + 2], nu, j);
+    if (pt.coupling[q] == 0) {
+      E = e * E + (1.0 - e) * jn_power(nu, pt.T[q]);
+      D = e * D;
+    } else {
+      E = e * E + (1.0 - e) * bcmb;
+      D = e * D + (1.0 - e) * (batm - bcmb);
+    }
+    W = e * W;
+  }
+  for (int i = 0; i < a.n_pwv; ++i)
+    a.tau[(int64_t)i * a.Fp + j] = (float)(-log(a.eta_z[(int64_t)i * a.F + j]));
+  // reference spectrum: zenith PWV ref_pwv, cosecant ref_csc, no source
+  double g = (a.ref_pwv - a.pwv0) / a.dpwv;
+  g = fmin(fmax(g, 0.0), (double)(a.n_pwv - 1));
+  int ci = (int)floor(g);
+  if (ci > a.n_pwv - 2) ci = a.n_pwv - 2;
+  const double wg = g - ci;
+  const double tz = (1.0 - wg) * (-log(a.eta_z[(int64_t)ci * a.F + j])) +
+                    wg * (-log(a.eta_z[(int64_t)(ci + 1) * a.F + j]));
+  const double xi = -expm1(-tz / sin(a.ref_el));
+  const float pref = (float)(E + xi * D);
+  a.E[j] = (float)E;
+  a.D[j] = (float)D;
+  a.W[j] = (float)W;
+  a.Pref[j] = pref;
+  a.Pref64[j] = (double)pref;
+}
+
+__global__ void k_filters(SpecSetupArgs a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.F) return;
+  const double nu = a.nu[j];
+  const double w = a.w[j];
+  const double hv = kH * nu;
+  const double gap = 2.0 * a.delta_J / a.eta_pb;
+  const bool cut = hv < 2.0 * a.delta_J;
+  const double pr = a.Pref64[j];
+  double absorbed = 0.0;
+  for (int q = 0; q < a.K; ++q) {
+    const int k = (a.mode == 1) ? a.order[q] : q;
+    double eta;
+    if (a.mode == 2) {
+      eta = a.eta_filt[(int64_t)j * a.K + k];
+    } else {
+      const double x = nu / a.f_hz[k] - 1.0;
+      const double L = 1.0 / (1.0 + 4.0 * a.R[k] * a.R[k] * x * x);
+      if (a.mode == 1) {
+        eta = (a.eta_peak[k] - absorbed) * L;
+        absorbed += eta;
+      } else {
+        eta = a.eta_peak[k] * L;
+      }
+    }
+    if (cut) eta = 0.0;
+    const double b0 = w * eta;
+    const double b1 = 2.0 * w * eta * (hv + gap);
+    const double b2 = 2.0 * w * eta * eta;
+    const int64_t FK = (int64_t)a.F * a.K;
+    a.B64[(int64_t)j * a.K + k] = b0;
+    a.B64[FK + (int64_t)j * a.K + k] = b1;
+    a.B64[2 * FK + (int64_t)j * a.K + k] = b2;
+    const int64_t KF = (int64_t)a.Kp * a.Fp;
+    const float v[3] = {(float)b0, (float)(b1 + 2.0 * pr * b2), (float)b2};
+    for (int m = 0; m < 3; ++m) {
+      const int64_t o = m * KF + (int64_t)k * a.Fp + j;
+      a.B[o] = v[m];
+      const uint16_t hi = bf16_rne(v[m]);
+      a.Bh[o] = hi;
+      a.Bl[o] = bf16_rne(v[m] - bf16_to_f(hi));
+    }
+  }
+}
+
+// c0[k] = sum_j Pref_j B0[j][k]; c1[k] = sum_j Pref_j B1 + Pref_j^2 B2.
+// One block per channel; fixed-order tree reduction in FP64.
+__global__ __launch_bounds__(256) void k_reference(SpecSetupArgs a) {
+  const int k = blockIdx.x;
+  __shared__ double s0[256], s1[256];
+  double acc0 = 0.0, acc1 = 0.0;
+  if (k < a.K) {
+    const int64_t FK = (int64_t)a.F * a.K;
+    for (int j = threadIdx.x; j < a.F; j += 256) {
+      const double p = a.Pref64[j];
+      const int64_t o = (int64_t)j * a.K + k;
+      acc0 += p * a.B64[o];
+      acc1 += p * a.B64[FK + o] + p * p * a.B64[2 * FK + o];
+    }
+  }
+  s0[threadIdx.x] = acc0;
+  s1[threadIdx.x] = acc1;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) {
+      s0[threadIdx.x] += s0[threadIdx.x + st];
+      s1[threadIdx.x] += s1[threadIdx.x + st];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.c0[k] = s0[0];
+    a.c1[k] = s1[0];
+  }
+}
+
+void launch_spec_setup(const SpecSetupArgs& a, const PassTable& pt,
+                       hipStream_t s) {
+  const int bs = 128;
+  hipLaunchKernelGGL(k_spectral, dim3((a.Fp + bs - 1) / bs), dim3(bs), 0, s,
+                     a, pt);
+  hipLaunchKernelGGL(k_filters, dim3((a.F + bs - 1) / bs), dim3(bs), 0, s, a);
+  hipLaunchKernelGGL(k_reference, dim3(a.Kp), dim3(256), 0, s, a);
+}
+
+}  // namespace gtod

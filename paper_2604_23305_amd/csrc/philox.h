@@ -1,0 +1,51 @@
+// Device-side Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the
+// uniform / Box-Muller maps the noise kernels use.
+//
+// One round maps (x0, x1, x2, x3) under key (k0, k1) to
+//   (hi(M1*x2) ^ x1 ^ k0, lo(M1*x2), hi(M0*x0) ^ x3 ^ k1, lo(M0*x0))
+// and the key advances by the Weyl constants between rounds.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gtod {
+
+struct u32x4 {
+  uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ u32x4 philox10(u32x4 c, uint32_t k0, uint32_t k1) {
+  constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
+  constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t lo0 = kM0 * c.x;
+    const uint32_t hi0 = __umulhi(kM0, c.x);
+    const uint32_t lo1 = kM1 * c.z;
+    const uint32_t hi1 = __umulhi(kM1, c.z);
+    c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    k0 += kW0;
+    k1 += kW1;
+  }
+  return c;
+}
+
+// ((o >> 9) + 1/2) * 2^-23: exact in FP32, strictly inside (0, 1).
+__device__ __forceinline__ float u01(uint32_t o) {
+  return (float)(o >> 9) * 1.1920928955078125e-07f + 5.9604644775390625e-08f;
+}
+
+// Box-Muller radius and the angle 2*pi*u1 evaluated as sincospi(2*u1),
+// whose argument is exact.
+__device__ __forceinline__ void box_muller(uint32_t o0, uint32_t o1,
+                                           float* zc, float* zs) {
+  const float r = sqrtf(-2.0f * logf(u01(o0)));
+  float s, c;
+  sincospif(2.0f * u01(o1), &s, &c);
+  *zc = r * c;
+  *zs = r * s;
+}
+
+}  // namespace gtod

@@ -1,0 +1,944 @@
+// Host runtime of the gtod C-ABI: contexts, the HBM budget, resident
+// screens and spectral setups, per-stream workspaces, job validation and
+// the enqueue of the panel / contraction / 1/f kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/gtod.h"
+#include "gtod_internal.h"
+
+using namespace gtod;
+
+namespace {
+
+struct ScreenObj {
+  double* pwv = nullptr;
+  int64_t nx = 0, ny = 0;
+  double dx = 0, dy = 0, ix0 = 0, iy0 = 0, h = 0, wind = 0;
+  double vmin = NAN, vmax = NAN;
+  size_t bytes = 0;
+};
+
+struct SpecObj {
+  int F = 0, Fp = 0, K = 0, Kp = 0, n_pwv = 0;
+  double pwv0 = 0, dpwv = 0;
+  float* tau = nullptr;
+  float* E = nullptr;
+  float* D = nullptr;
+  float* W = nullptr;
+  float* Pref = nullptr;
+  float* B = nullptr;
+  uint16_t* Bh = nullptr;
+  uint16_t* Bl = nullptr;
+  double* c0 = nullptr;
+  double* c1 = nullptr;
+  std::vector<double> nep2ref;
+  std::vector<void*> allocs;
+};
+
+constexpr int kSlots = 8;
+constexpr size_t kSlotBytes = 1 << 20;
+
+struct StreamWs {
+  hipStream_t stream = nullptr;
+  float* panel = nullptr;
+  size_t panel_bytes = 0;
+  float2* pink = nullptr;
+  size_t pink_bytes = 0;
+  char* h_stage = nullptr;
+  char* d_stage = nullptr;
+  hipEvent_t ev[kSlots] = {};
+  bool ev_used[kSlots] = {};
+  int slot = 0;
+};
+
+}  // namespace
+
+struct gtod_ctx {
+  int device = 0;
+  int precision = GTOD_PREC_FP32;
+  uint32_t flags = 0;
+  uint64_t budget = 0, used = 0, ws_bytes = 0;
+  double fs = 0, eta_taper = 0, rho_surf = 0, eta_pol = 0, delta_J = 0,
+         eta_pb = 0, t_cmb = 0;
+  std::map<int32_t, ScreenObj> screens;
+  std::map<int32_t, SpecObj> specs;
+  int32_t next_id = 1;
+  std::map<void*, size_t> sizes;
+  std::map<hipStream_t, StreamWs> ws;
+  unsigned long long* counters = nullptr;
+  std::string err;
+  // profiling
+  bool prof = false;
+  struct Rec { int kernel; hipEvent_t a, b; double units; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[GTOD_N_KERNELS] = {}, prof_n[GTOD_N_KERNELS] = {},
+         prof_units[GTOD_N_KERNELS] = {};
+};
+
+namespace {
+
+std::string g_init_err;
+
+gtod_status fail(gtod_ctx* c, gtod_status st, const std::string& msg) {
+  if (c) c->err = msg; else g_init_err = msg;
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                  \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(ctx, GTOD_EDEVICE,                                        \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+gtod_status dev_alloc(gtod_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 256;
+  if (c->used + bytes > c->budget)
+    return fail(c, GTOD_EBUDGET, "allocation of " + std::to_string(bytes) +
+                                     " bytes exceeds the HBM budget");
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(c, GTOD_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  c->used += bytes;
+  c->sizes[*p] = bytes;
+  return GTOD_OK;
+}
+
+void dev_free(gtod_ctx* c, void* p) {
+  if (!p) return;
+  auto it = c->sizes.find(p);
+  if (it != c->sizes.end()) {
+    c->used -= it->second;
+    c->sizes.erase(it);
+  }
+  (void)hipFree(p);
+}
+
+void free_spec(gtod_ctx* c, SpecObj& s) {
+  for (void* p : s.allocs) dev_free(c, p);
+  s.allocs.clear();
+}
+
+void free_ws(gtod_ctx* c, StreamWs& w) {
+  dev_free(c, w.panel);
+  dev_free(c, w.pink);
+  dev_free(c, w.d_stage);
+  if (w.h_stage) (void)hipHostFree(w.h_stage);
+  for (int i = 0; i < kSlots; ++i)
+    if (w.ev[i]) (void)hipEventDestroy(w.ev[i]);
+  w = StreamWs{};
+}
+
+gtod_status get_ws(gtod_ctx* c, hipStream_t s, StreamWs** out) {
+  auto it = c->ws.find(s);
+  if (it != c->ws.end()) {
+    *out = &it->second;
+    return GTOD_OK;
+  }
+  StreamWs w;
+  w.stream = s;
+  w.panel_bytes = round_up((int64_t)(c->ws_bytes * 3 / 4), 256);
+  w.pink_bytes = round_up((int64_t)(c->ws_bytes - w.panel_bytes), 256);
+  gtod_status st;
+  if ((st = dev_alloc(c, (void**)&w.panel, w.panel_bytes)) != GTOD_OK ||
+      (st = dev_alloc(c, (void**)&w.pink, w.pink_bytes)) != GTOD_OK ||
+      (st = dev_alloc(c, (void**)&w.d_stage, kSlots * kSlotBytes)) != GTOD_OK) {
+    free_ws(c, w);
+    return st;
+  }
+  if (hipHostMalloc((void**)&w.h_stage, kSlots * kSlotBytes, hipHostMallocDefault) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    free_ws(c, w);
+    return fail(c, GTOD_ENOMEM, "pinned staging allocation failed");
+  }
+  for (int i = 0; i < kSlots; ++i) {
+    if (hipEventCreateWithFlags(&w.ev[i], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      free_ws(c, w);
+      return fail(c, GTOD_EDEVICE, "event creation failed");
+    }
+  }
+  auto res = c->ws.emplace(s, w);
+  *out = &res.first->second;
+  return GTOD_OK;
+}
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+hipEvent_t pool_event(gtod_ctx* c) {
+  if (!c->ev_pool.empty()) {
+    hipEvent_t e = c->ev_pool.back();
+    c->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Runs launch() on stream s; with profiling on, brackets it by events.
+template <class Fn>
+void timed(gtod_ctx* c, int kernel, double units, hipStream_t s, Fn launch) {
+  if (!c->prof) {
+    launch();
+    return;
+  }
+  hipEvent_t a = pool_event(c), b = pool_event(c);
+  if (a && b) (void)hipEventRecord(a, s);
+  launch();
+  if (a && b) {
+    (void)hipEventRecord(b, s);
+    c->recs.push_back({kernel, a, b, units});
+  }
+}
+
+void drain_profile(gtod_ctx* c) {
+  for (auto& r : c->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->prof_ms[r.kernel] += ms;
+      c->prof_n[r.kernel] += 1;
+      c->prof_units[r.kernel] += r.units;
+    } else {
+      (void)hipGetLastError();
+    }
+    c->ev_pool.push_back(r.a);
+    c->ev_pool.push_back(r.b);
+  }
+  c->recs.clear();
+}
+
+struct JobPlan {
+  const gtod_job* j;
+  const ScreenObj* scr;
+  const SpecObj* spec;
+  int precision;
+  size_t off_dphi, off_dtheta, off_scale, off_alpha;
+};
+
+gtod_status validate(gtod_ctx* c, const gtod_job& j, int idx, JobPlan* pl) {
+  const std::string at = "job " + std::to_string(idx) + ": ";
+  if (j.kind != GTOD_JOB_SIGNAL && j.kind != GTOD_JOB_PINK)
+    return fail(c, GTOD_EINVAL, at + "unknown kind");
+  auto sp = c->specs.find(j.spec_id);
+  if (sp == c->specs.end()) return fail(c, GTOD_ENOTFOUND, at + "unknown spec_id");
+  pl->spec = &sp->second;
+  pl->scr = nullptr;
+  if (j.n_pix < 1) return fail(c, GTOD_EINVAL, at + "n_pix < 1");
+  if (!j.tod) return fail(c, GTOD_EINVAL, at + "tod is NULL");
+  if (j.t_total < 1 || j.t_total > (int64_t)1 << 31)
+    return fail(c, GTOD_EINVAL, at + "t_total out of range");
+  if (j.flags & ~(GTOD_JOB_PHOTON_NOISE | GTOD_JOB_ACCUMULATE))
+    return fail(c, GTOD_EINVAL, at + "unknown flags");
+  const int prec = j.precision < 0 ? c->precision : j.precision;
+  if (prec != GTOD_PREC_FP32 && prec != GTOD_PREC_SPLIT_BF16)
+    return fail(c, GTOD_EINVAL, at + "unknown precision");
+  pl->precision = prec;
+  if (j.kind == GTOD_JOB_PINK) {
+    if (!j.pink_alpha) return fail(c, GTOD_EINVAL, at + "pink_alpha is NULL");
+    if (!finite_pos(j.pink_knee_hz)) return fail(c, GTOD_EINVAL, at + "pink_knee_hz must be > 0");
+    if ((int64_t)j.n_pix * pl->spec->K > ((int64_t)1 << 31))
+      return fail(c, GTOD_EINVAL, at + "too many series");
+    for (int k = 0; k < pl->spec->K; ++k)
+      if (!std::isfinite(j.pink_alpha[k]))
+        return fail(c, GTOD_EINVAL, at + "pink_alpha not finite");
+    return GTOD_OK;
+  }
+  auto sc = c->screens.find(j.screen_id);
+  if (sc == c->screens.end()) return fail(c, GTOD_ENOTFOUND, at + "unknown screen_id");
+  pl->scr = &sc->second;
+  if (!j.dphi_rad || !j.dtheta_rad) return fail(c, GTOD_EINVAL, at + "pixel offsets are NULL");
+  if (j.t_begin < 0 || j.t_end > j.t_total || j.t_begin > j.t_end)
+    return fail(c, GTOD_EINVAL, at + "bad [t_begin, t_end)");
+  if (j.scan_kind < 0 || j.scan_kind > 2) return fail(c, GTOD_EINVAL, at + "unknown scan kind");
+  if (j.scan_kind == GTOD_SCAN_TRAJ && !j.traj)
+    return fail(c, GTOD_EINVAL, at + "TRAJ scan without trajectory");
+  if (j.cube) {
+    if (j.n_az < 2 || j.n_el < 2) return fail(c, GTOD_EINVAL, at + "source grid needs >= 2 nodes per axis");
+    if (j.cube_ld < pl->spec->F) return fail(c, GTOD_EINVAL, at + "cube_ld < F");
+    if (!(j.daz_rad > 0) || !(j.del_rad > 0)) return fail(c, GTOD_EINVAL, at + "source grid spacing must be > 0");
+  }
+  double rmax = 0;
+  if (j.scan_kind == GTOD_SCAN_DAISY) {
+    rmax = std::fabs(j.scan_params[0]);
+    for (int q = 0; q < 3; ++q)
+      if (!std::isfinite(j.scan_params[q])) return fail(c, GTOD_EINVAL, at + "daisy parameters not finite");
+  }
+  double dpmin = 1e300, dpmax = -1e300, dtmin = 1e300, dtmax = -1e300;
+  for (int p = 0; p < j.n_pix; ++p) {
+    if (!std::isfinite(j.dphi_rad[p]) || !std::isfinite(j.dtheta_rad[p]))
+      return fail(c, GTOD_EINVAL, at + "pixel offsets not finite");
+    dpmin = std::min(dpmin, j.dphi_rad[p]);
+    dpmax = std::max(dpmax, j.dphi_rad[p]);
+    dtmin = std::min(dtmin, j.dtheta_rad[p]);
+    dtmax = std::max(dtmax, j.dtheta_rad[p]);
+  }
+  if (j.scan_kind != GTOD_SCAN_TRAJ) {
+    const double elo = j.theta0_rad + dtmin - rmax, ehi = j.theta0_rad + dtmax + rmax;
+    if (!(elo > 0.0 && ehi < M_PI)) return fail(c, GTOD_EINVAL, at + "elevation leaves (0, pi)");
+    if (c->flags & GTOD_INIT_STRICT_RANGE) {
+      const ScreenObj& s = *pl->scr;
+      const double t0 = j.t_begin / c->fs, t1 = std::max<int64_t>(j.t_end - 1, j.t_begin) / c->fs;
+      const double w0 = std::min(s.wind * t0, s.wind * t1), w1 = std::max(s.wind * t0, s.wind * t1);
+      const double xlo = s.h * std::tan(dpmin - rmax) + w0, xhi = s.h * std::tan(dpmax + rmax) + w1;
+      const double ylo = s.h * std::tan(dtmin - rmax), yhi = s.h * std::tan(dtmax + rmax);
+      const double gx0 = xlo / s.dx + s.ix0, gx1 = xhi / s.dx + s.ix0;
+      const double gy0 = ylo / s.dy + s.iy0, gy1 = yhi / s.dy + s.iy0;
+      if (gx0 < 0 || gx1 > s.nx - 1 || gy0 < 0 || gy1 > s.ny - 1)
+        return fail(c, GTOD_ERANGE, at + "pointing leaves the screen");
+      const SpecObj& f = *pl->spec;
+      if (std::isfinite(s.vmin) &&
+          (s.vmin < f.pwv0 || s.vmax > f.pwv0 + (f.n_pwv - 1) * f.dpwv))
+        return fail(c, GTOD_ERANGE, at + "screen PWV leaves the table axis");
+    }
+  }
+  return GTOD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gtod_status gtod_sim_init(const gtod_init_desc* d, gtod_ctx** out) {
+  if (!out) return fail(nullptr, GTOD_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(nullptr, GTOD_EINVAL, "desc is NULL");
+  if (!finite_pos(d->f_sample_hz)) return fail(nullptr, GTOD_EINVAL, "f_sample_hz must be > 0");
+  if (!finite_pos(d->eta_pb)) return fail(nullptr, GTOD_EINVAL, "eta_pb must be > 0");
+  if (d->precision != GTOD_PREC_FP32 && d->precision != GTOD_PREC_SPLIT_BF16)
+    return fail(nullptr, GTOD_EINVAL, "unknown precision");
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || d->device < 0 || d->device >= ndev) {
+    (void)hipGetLastError();
+    return fail(nullptr, GTOD_EINVAL, "no such device");
+  }
+  if (hipSetDevice(d->device) != hipSuccess) return fail(nullptr, GTOD_EDEVICE, "hipSetDevice failed");
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, d->device) != hipSuccess)
+    return fail(nullptr, GTOD_EDEVICE, "hipGetDeviceProperties failed");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, GTOD_EUNSUPPORTED, std::string("device is ") + prop.gcnArchName + ", not gfx950");
+  auto* c = new gtod_ctx;
+  c->device = d->device;
+  c->precision = d->precision;
+  c->flags = d->flags;
+  size_t free_b = 0, total_b = 0;
+  (void)hipMemGetInfo(&free_b, &total_b);
+  c->budget = d->hbm_budget_bytes ? d->hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+  c->ws_bytes = d->workspace_bytes ? d->workspace_bytes : (1ull << 30);
+  c->fs = d->f_sample_hz;
+  c->eta_taper = d->eta_taper;
+  c->rho_surf = d->rho_surf_m;
+  c->eta_pol = d->eta_pol;
+  c->delta_J = d->delta_J;
+  c->eta_pb = d->eta_pb;
+  c->t_cmb = d->t_cmb_K;
+  gtod_status st = dev_alloc(c, (void**)&c->counters, 2 * sizeof(unsigned long long));
+  if (st != GTOD_OK) {
+    g_init_err = c->err;
+    delete c;
+    return st;
+  }
+  if (hipMemset(c->counters, 0, 2 * sizeof(unsigned long long)) != hipSuccess) {
+    dev_free(c, c->counters);
+    delete c;
+    return fail(nullptr, GTOD_EDEVICE, "hipMemset failed");
+  }
+  *out = c;
+  return GTOD_OK;
+}
+
+gtod_status gtod_load_screen(gtod_ctx* c, const gtod_screen_desc* d, int32_t* id) {
+  if (!c || !d || !id) return fail(c, GTOD_EINVAL, "NULL argument");
+  if (!d->pwv_mm || d->nx < 2 || d->ny < 2) return fail(c, GTOD_EINVAL, "screen needs nx, ny >= 2");
+  if (!finite_pos(d->dx_m) || !finite_pos(d->dy_m)) return fail(c, GTOD_EINVAL, "cell size must be > 0");
+  if (!std::isfinite(d->h_column_m) || !std::isfinite(d->wind_mps) ||
+      !std::isfinite(d->ix0) || !std::isfinite(d->iy0))
+    return fail(c, GTOD_EINVAL, "screen parameters not finite");
+  if (d->mem_kind != 0 && d->mem_kind != 1) return fail(c, GTOD_EINVAL, "unknown mem_kind");
+  HIP_TRY(c, hipSetDevice(c->device));
+  ScreenObj s;
+  s.nx = d->nx;
+  s.ny = d->ny;
+  s.dx = d->dx_m;
+  s.dy = d->dy_m;
+  s.ix0 = d->ix0;
+  s.iy0 = d->iy0;
+  s.h = d->h_column_m;
+  s.wind = d->wind_mps;
+  s.bytes = (size_t)s.nx * s.ny * sizeof(double);
+  gtod_status st = dev_alloc(c, (void**)&s.pwv, s.bytes);
+  if (st != GTOD_OK) return st;
+  if (d->mem_kind == 0) {
+    double lo = INFINITY, hi = -INFINITY;
+    const int64_t n = s.nx * s.ny;
+    for (int64_t i = 0; i < n; ++i) {
+      lo = std::min(lo, d->pwv_mm[i]);
+      hi = std::max(hi, d->pwv_mm[i]);
+    }
+    s.vmin = lo;
+    s.vmax = hi;
+  }
+  hipError_t e = hipMemcpy(s.pwv, d->pwv_mm, s.bytes,
+                           d->mem_kind == 0 ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice);
+  if (e != hipSuccess) {
+    dev_free(c, s.pwv);
+    return fail(c, GTOD_EDEVICE, std::string("screen copy: ") + hipGetErrorString(e));
+  }
+  *id = c->next_id++;
+  c->screens[*id] = s;
+  return GTOD_OK;
+}
+
+gtod_status gtod_load_filters(gtod_ctx* c, const gtod_spectral_desc* d, int32_t* id) {
+  if (!c || !d || !id) return fail(c, GTOD_EINVAL, "NULL argument");
+  const int F = d->F, K = d->K;
+  if (F < 1 || K < 1 || d->n_pwv < 2) return fail(c, GTOD_EINVAL, "need F >= 1, K >= 1, n_pwv >= 2");
+  if (!d->nu_hz || !d->w_hz || !d->eta_z) return fail(c, GTOD_EINVAL, "NULL spectral array");
+  if (!finite_pos(d->dpwv_mm) || !std::isfinite(d->pwv0_mm)) return fail(c, GTOD_EINVAL, "bad PWV axis");
+  if (d->n_stage < 0 || (d->n_stage > 0 && !d->stages)) return fail(c, GTOD_EINVAL, "bad stage list");
+  if (d->filter_mode < 0 || d->filter_mode > 2) return fail(c, GTOD_EINVAL, "unknown filter mode");
+  if (d->filter_mode == GTOD_FILT_MATRIX ? !d->eta_filt : (!d->f_hz || !d->R || !d->eta_peak))
+    return fail(c, GTOD_EINVAL, "missing filter parameters");
+  if (!(d->ref_el_rad > 0 && d->ref_el_rad < M_PI)) return fail(c, GTOD_EINVAL, "ref_el_rad outside (0, pi)");
+  for (int j = 0; j < F; ++j)
+    if (!finite_pos(d->nu_hz[j]) || !finite_pos(d->w_hz[j]))
+      return fail(c, GTOD_EINVAL, "nu and w must be positive");
+  for (int64_t i = 0; i < (int64_t)d->n_pwv * F; ++i)
+    if (!(d->eta_z[i] > 0.0 && d->eta_z[i] <= 1.0))
+      return fail(c, GTOD_EINVAL, "eta_z must lie in (0, 1]");
+  if (d->filter_mode != GTOD_FILT_MATRIX)
+    for (int k = 0; k < K; ++k)
+      if (!finite_pos(d->f_hz[k]) || !finite_pos(d->R[k]) || !std::isfinite(d->eta_peak[k]))
+        return fail(c, GTOD_EINVAL, "bad channel parameters");
+
+  // optics stages -> passes (a refractive stage is surface, absorption,
+  // surface; AR-coated keeps the absorption only)
+  std::vector<int> ptype, pcoup, poff;
+  std::vector<double> pprm, pT, pool;
+  for (int s = 0; s < d->n_stage; ++s) {
+    const gtod_stage& g = d->stages[s];
+    auto add = [&](int type, int coup, double a0, double a1, double a2, double T, int off) {
+      ptype.push_back(type);
+      pcoup.push_back(coup);
+      poff.push_back(off);
+      pprm.push_back(a0);
+      pprm.push_back(a1);
+      pprm.push_back(a2);
+      pT.push_back(T);
+    };
+    switch (g.kind) {
+      case GTOD_STAGE_REFLECT:
+      case GTOD_STAGE_ATM_COUPLED: {
+        const int coup = g.kind == GTOD_STAGE_ATM_COUPLED;
+        if (g.eta) {
+          const int off = (int)pool.size();
+          pool.insert(pool.end(), g.eta, g.eta + F);
+          add(0, coup, 0, 0, 0, g.t_K, off);
+        } else {
+          add(1, coup, g.eta_const, 0, 0, g.t_K, 0);
+        }
+        break;
+      }
+      case GTOD_STAGE_OHMIC:
+        if (!finite_pos(g.nu_ref_hz)) return fail(c, GTOD_EINVAL, "Ohmic stage needs nu_ref_hz > 0");
+        add(2, 0, g.eps_ref, g.nu_ref_hz, 0, g.t_K, 0);
+        break;
+      case GTOD_STAGE_REFRACTIVE:
+        if (!finite_pos(g.n_index)) return fail(c, GTOD_EINVAL, "refractive stage needs n > 0");
+        if (!g.ar_coated) add(4, 0, g.n_index, 0, 0, g.t_refl_K, 0);
+        add(3, 0, g.d_m, g.n_index, g.tan_delta, g.t_K, 0);
+        if (!g.ar_coated) add(4, 0, g.n_index, 0, 0, g.t_refl_K, 0);
+        break;
+      default:
+        return fail(c, GTOD_EINVAL, "unknown stage kind");
+    }
+  }
+  if (pool.empty()) pool.push_back(0.0);
+  const int n_pass = (int)ptype.size();
+  std::vector<int> order(K);
+  std::iota(order.begin(), order.end(), 0);
+  if (d->filter_mode == GTOD_FILT_FILTERBANK)
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return d->f_hz[a] > d->f_hz[b]; });
+
+  HIP_TRY(c, hipSetDevice(c->device));
+  SpecObj so;
+  so.F = F;
+  so.K = K;
+  so.Fp = (int)round_up(F, kFPad);
+  so.Kp = (int)round_up(K, kKPad);
+  so.n_pwv = d->n_pwv;
+  so.pwv0 = d->pwv0_mm;
+  so.dpwv = d->dpwv_mm;
+  const int64_t Fp = so.Fp, Kp = so.Kp;
+  gtod_status st = GTOD_OK;
+  auto res = [&](void** p, size_t bytes) {
+    if (st != GTOD_OK) return;
+    st = dev_alloc(c, p, bytes);
+    if (st == GTOD_OK) so.allocs.push_back(*p);
+  };
+  res((void**)&so.tau, (size_t)d->n_pwv * Fp * 4);
+  res((void**)&so.E, Fp * 4);
+  res((void**)&so.D, Fp * 4);
+  res((void**)&so.W, Fp * 4);
+  res((void**)&so.Pref, Fp * 4);
+  res((void**)&so.B, 3 * Kp * Fp * 4);
+  res((void**)&so.Bh, 3 * Kp * Fp * 2);
+  res((void**)&so.Bl, 3 * Kp * Fp * 2);
+  res((void**)&so.c0, Kp * 8);
+  res((void**)&so.c1, Kp * 8);
+  // temporaries
+  std::vector<void*> tmp;
+  auto tmpa = [&](void** p, size_t bytes) {
+    if (st != GTOD_OK) return;
+    st = dev_alloc(c, p, bytes);
+    if (st == GTOD_OK) tmp.push_back(*p);
+  };
+  double *d_nu, *d_w, *d_eta, *d_pool, *d_prm, *d_T, *d_f = nullptr, *d_R = nullptr,
+         *d_pk = nullptr, *d_mat = nullptr, *d_pref64, *d_B64;
+  int *d_type, *d_coup, *d_off, *d_order;
+  tmpa((void**)&d_nu, F * 8);
+  tmpa((void**)&d_w, F * 8);
+  tmpa((void**)&d_eta, (size_t)d->n_pwv * F * 8);
+  tmpa((void**)&d_pool, pool.size() * 8);
+  tmpa((void**)&d_prm, std::max<size_t>(pprm.size(), 1) * 8);
+  tmpa((void**)&d_T, std::max<size_t>(pT.size(), 1) * 8);
+  tmpa((void**)&d_type, std::max<size_t>(ptype.size(), 1) * 4);
+  tmpa((void**)&d_coup, std::max<size_t>(pcoup.size(), 1) * 4);
+  tmpa((void**)&d_off, std::max<size_t>(poff.size(), 1) * 4);
+  tmpa((void**)&d_order, K * 4);
+  tmpa((void**)&d_pref64, Fp * 8);
+  tmpa((void**)&d_B64, (size_t)3 * F * K * 8);
+  if (d->filter_mode == GTOD_FILT_MATRIX) {
+    tmpa((void**)&d_mat, (size_t)F * K * 8);
+  } else {
+    tmpa((void**)&d_f, K * 8);
+    tmpa((void**)&d_R, K * 8);
+    tmpa((void**)&d_pk, K * 8);
+  }
+  auto cleanup = [&]() {
+    for (void* p : tmp) dev_free(c, p);
+    tmp.clear();
+  };
+  if (st != GTOD_OK) {
+    cleanup();
+    free_spec(c, so);
+    return st;
+  }
+  hipError_t e = hipSuccess;
+  auto cp = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes) e = hipMemcpy(dst, src, bytes, hipMemcpyHostToDevice);
+  };
+  cp(d_nu, d->nu_hz, F * 8);
+  cp(d_w, d->w_hz, F * 8);
+  cp(d_eta, d->eta_z, (size_t)d->n_pwv * F * 8);
+  cp(d_pool, pool.data(), pool.size() * 8);
+  cp(d_prm, pprm.data(), pprm.size() * 8);
+  cp(d_T, pT.data(), pT.size() * 8);
+  cp(d_type, ptype.data(), ptype.size() * 4);
+  cp(d_coup, pcoup.data(), pcoup.size() * 4);
+  cp(d_off, poff.data(), poff.size() * 4);
+  cp(d_order, order.data(), K * 4);
+  if (d_mat) cp(d_mat, d->eta_filt, (size_t)F * K * 8);
+  if (d_f) {
+    cp(d_f, d->f_hz, K * 8);
+    cp(d_R, d->R, K * 8);
+    cp(d_pk, d->eta_peak, K * 8);
+  }
+  if (e == hipSuccess) e = hipMemset(so.B, 0, 3 * Kp * Fp * 4);
+  if (e == hipSuccess) e = hipMemset(so.Bh, 0, 3 * Kp * Fp * 2);
+  if (e == hipSuccess) e = hipMemset(so.Bl, 0, 3 * Kp * Fp * 2);
+  if (e == hipSuccess) {
+    SpecSetupArgs a{};
+    a.F = F;
+    a.Fp = so.Fp;
+    a.K = K;
+    a.Kp = so.Kp;
+    a.n_pwv = d->n_pwv;
+    a.mode = d->filter_mode;
+    a.nu = d_nu;
+    a.w = d_w;
+    a.eta_z = d_eta;
+    a.f_hz = d_f;
+    a.R = d_R;
+    a.eta_peak = d_pk;
+    a.order = d_order;
+    a.eta_filt = d_mat;
+    a.t_atm = d->t_atm_K;
+    a.t_cmb = c->t_cmb;
+    a.eta_taper = c->eta_taper;
+    a.rho_surf = c->rho_surf;
+    a.eta_pol = c->eta_pol;
+    a.delta_J = c->delta_J;
+    a.eta_pb = c->eta_pb;
+    a.ref_pwv = d->ref_pwv_mm;
+    a.pwv0 = d->pwv0_mm;
+    a.dpwv = d->dpwv_mm;
+    a.ref_el = d->ref_el_rad;
+    a.tau = so.tau;
+    a.E = so.E;
+    a.D = so.D;
+    a.W = so.W;
+    a.Pref = so.Pref;
+    a.Pref64 = d_pref64;
+    a.B64 = d_B64;
+    a.B = so.B;
+    a.Bh = so.Bh;
+    a.Bl = so.Bl;
+    a.c0 = so.c0;
+    a.c1 = so.c1;
+    PassTable pt{n_pass, d_type, d_coup, d_off, d_prm, d_T, d_pool};
+    launch_spec_setup(a, pt, nullptr);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+  }
+  if (e == hipSuccess) {
+    so.nep2ref.resize(K);
+    e = hipMemcpy(so.nep2ref.data(), so.c1, K * 8, hipMemcpyDeviceToHost);
+  }
+  cleanup();
+  if (e != hipSuccess) {
+    free_spec(c, so);
+    return fail(c, GTOD_EDEVICE, std::string("spectral setup: ") + hipGetErrorString(e));
+  }
+  *id = c->next_id++;
+  c->specs[*id] = so;
+  return GTOD_OK;
+}
+
+gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
+                              void* hip_stream) {
+  if (!c) return GTOD_EINVAL;
+  if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(c, GTOD_EINVAL, "bad job array");
+  if (n_jobs == 0) return GTOD_OK;
+  std::vector<JobPlan> plan(n_jobs);
+  size_t stage_bytes = 0;
+  for (int i = 0; i < n_jobs; ++i) {
+    plan[i].j = &jobs[i];
+    gtod_status st = validate(c, jobs[i], i, &plan[i]);
+    if (st != GTOD_OK) return st;
+    const gtod_job& j = jobs[i];
+    if (j.kind == GTOD_JOB_SIGNAL) {
+      plan[i].off_dphi = stage_bytes;
+      stage_bytes += round_up((int64_t)j.n_pix * 8, 256);
+      plan[i].off_dtheta = stage_bytes;
+      stage_bytes += round_up((int64_t)j.n_pix * 8, 256);
+    } else {
+      const int K = plan[i].spec->K;
+      plan[i].off_scale = stage_bytes;
+      stage_bytes += round_up((int64_t)K * 4, 256);
+      plan[i].off_alpha = stage_bytes;
+      stage_bytes += round_up((int64_t)K * 4, 256);
+    }
+  }
+  if (stage_bytes > kSlotBytes) return fail(c, GTOD_EINVAL, "per-call job parameters exceed 1 MiB");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  StreamWs* w = nullptr;
+  gtod_status st = get_ws(c, s, &w);
+  if (st != GTOD_OK) return st;
+
+  // stage the small per-job arrays through a pinned slot
+  const int slot = w->slot;
+  w->slot = (w->slot + 1) % kSlots;
+  if (w->ev_used[slot]) HIP_TRY(c, hipEventSynchronize(w->ev[slot]));
+  char* hs = w->h_stage + (size_t)slot * kSlotBytes;
+  char* ds = w->d_stage + (size_t)slot * kSlotBytes;
+  for (int i = 0; i < n_jobs; ++i) {
+    const gtod_job& j = jobs[i];
+    if (j.kind == GTOD_JOB_SIGNAL) {
+      std::memcpy(hs + plan[i].off_dphi, j.dphi_rad, (size_t)j.n_pix * 8);
+      std::memcpy(hs + plan[i].off_dtheta, j.dtheta_rad, (size_t)j.n_pix * 8);
+    } else {
+      const SpecObj& f = *plan[i].spec;
+      const int64_t N = [&] { int64_t n = 2; while (n < j.t_total) n *= 2; return n; }();
+      float* scale = (float*)(hs + plan[i].off_scale);
+      float* alpha = (float*)(hs + plan[i].off_alpha);
+      for (int k = 0; k < f.K; ++k) {
+        const double A = f.nep2ref[k] * std::pow(j.pink_knee_hz, j.pink_alpha[k]);
+        scale[k] = (float)(std::sqrt(A * (double)N * c->fs / 4.0) / (double)N);
+        alpha[k] = (float)j.pink_alpha[k];
+      }
+    }
+  }
+  HIP_TRY(c, hipMemcpyAsync(ds, hs, stage_bytes, hipMemcpyHostToDevice, s));
+
+  for (int i = 0; i < n_jobs; ++i) {
+    const gtod_job& j = jobs[i];
+    const SpecObj& f = *plan[i].spec;
+    const uint32_t key0 = (uint32_t)(j.seed & 0xFFFFFFFFull);
+    const uint32_t key1 = (uint32_t)(j.seed >> 32);
+    const bool acc = (j.flags & GTOD_JOB_ACCUMULATE) != 0;
+    if (j.kind == GTOD_JOB_PINK) {
+      PinkArgs a{};
+      int64_t N = 2;
+      while (N < j.t_total) N *= 2;
+      const int lgM = (int)std::log2((double)(N / 2));
+      a.M = (int)(N / 2);
+      a.lgM2 = std::min(lgM, 12);
+      a.lgM1 = lgM - a.lgM2;
+      a.M1 = 1 << a.lgM1;
+      a.M2 = 1 << a.lgM2;
+      a.N = (int)N;
+      a.B2 = std::min(16, 4096 / a.M1);
+      a.fs = c->fs;
+      a.K = f.K;
+      a.scale = (const float*)(ds + plan[i].off_scale);
+      a.alpha = (const float*)(ds + plan[i].off_alpha);
+      a.key0 = key0;
+      a.key1 = key1;
+      a.tod = j.tod;
+      a.t_total = j.t_total;
+      a.accumulate = acc;
+      a.scratch = w->pink;
+      const int64_t S = (int64_t)j.n_pix * f.K;
+      int64_t per = a.M1 > 1 ? (int64_t)(w->pink_bytes / ((size_t)a.M * sizeof(float2))) : S;
+      per = std::min<int64_t>(std::min<int64_t>(per, S), 65535);
+      if (per < 1) return fail(c, GTOD_EINVAL, "1/f series longer than the workspace");
+      for (int64_t s0 = 0; s0 < S; s0 += per) {
+        a.s0 = s0;
+        a.n_series = (int)std::min<int64_t>(per, S - s0);
+        const double pts = (double)a.n_series * a.M;
+        timed(c, GTOD_KERNEL_PINK1, pts, s, [&] { launch_pink_pass1(a, s); });
+        if (a.M1 > 1)
+          timed(c, GTOD_KERNEL_PINK2, pts, s, [&] { launch_pink_pass2(a, s); });
+      }
+      continue;
+    }
+    const ScreenObj& sc = *plan[i].scr;
+    const int64_t T = j.t_end - j.t_begin;
+    if (T == 0) continue;
+    const int64_t rows_cap = (int64_t)(w->panel_bytes / ((size_t)f.Fp * 4));
+    int pg;          // pixels per chunk
+    int64_t Tc_max;  // samples per chunk
+    if ((int64_t)j.n_pix * kRowPad <= rows_cap) {
+      pg = j.n_pix;
+      Tc_max = std::max<int64_t>(kRowPad, rows_cap / j.n_pix / kRowPad * kRowPad);
+    } else {
+      pg = (int)std::max<int64_t>(1, rows_cap / kRowPad);
+      Tc_max = kRowPad;
+    }
+    if ((int64_t)pg * kRowPad > rows_cap)
+      return fail(c, GTOD_EINVAL, "frequency axis too long for the workspace");
+    Tc_max = std::min<int64_t>(Tc_max, round_up(T, kRowPad));
+    PanelArgs pa{};
+    pa.tau = f.tau;
+    pa.E = f.E;
+    pa.D = f.D;
+    pa.W = f.W;
+    pa.Pref = f.Pref;
+    pa.F = f.F;
+    pa.Fp = f.Fp;
+    pa.n_pwv = f.n_pwv;
+    pa.pwv0 = f.pwv0;
+    pa.dpwv = f.dpwv;
+    pa.scr = sc.pwv;
+    pa.nx = sc.nx;
+    pa.ny = sc.ny;
+    pa.dx = sc.dx;
+    pa.dy = sc.dy;
+    pa.ix0 = sc.ix0;
+    pa.iy0 = sc.iy0;
+    pa.h = sc.h;
+    pa.wind = sc.wind;
+    pa.scan_kind = j.scan_kind;
+    pa.phi0 = j.phi0_rad;
+    pa.theta0 = j.theta0_rad;
+    pa.r_petal = j.scan_params[0];
+    pa.omega = j.scan_params[1];
+    pa.Omega = j.scan_params[2];
+    pa.traj = j.traj;
+    pa.f_s = c->fs;
+    pa.dphi = (const double*)(ds + plan[i].off_dphi);
+    pa.dtheta = (const double*)(ds + plan[i].off_dtheta);
+    pa.cube = j.cube;
+    pa.n_az = j.n_az;
+    pa.n_el = j.n_el;
+    pa.cube_ld = j.cube_ld;
+    pa.az0 = j.az0_rad;
+    pa.daz = j.daz_rad;
+    pa.el0 = j.el0_rad;
+    pa.del = j.del_rad;
+    pa.panel = w->panel;
+    pa.pwv_out = j.pwv;
+    pa.t_total = j.t_total;
+    pa.counters = c->counters;
+    GemmArgs ga{};
+    ga.panel = w->panel;
+    ga.B = f.B;
+    ga.Bh = f.Bh;
+    ga.Bl = f.Bl;
+    ga.c0 = f.c0;
+    ga.c1 = f.c1;
+    ga.Fp = f.Fp;
+    ga.K = f.K;
+    ga.Kp = f.Kp;
+    ga.t_total = j.t_total;
+    ga.fs_half = (float)(0.5 * c->fs);
+    ga.key0 = key0;
+    ga.key1 = key1;
+    ga.photon = (j.flags & GTOD_JOB_PHOTON_NOISE) != 0;
+    ga.accumulate = acc;
+    ga.tod = j.tod;
+    ga.p_kid = j.p_kid;
+    ga.sigma = j.sigma;
+    for (int p0 = 0; p0 < j.n_pix; p0 += pg) {
+      const int np = std::min(pg, j.n_pix - p0);
+      for (int64_t tb = j.t_begin; tb < j.t_end; tb += Tc_max) {
+        const int Tc = (int)std::min<int64_t>(Tc_max, j.t_end - tb);
+        const int Tpad = (int)round_up(Tc, kRowPad);
+        pa.p0 = p0;
+        pa.n_pix = np;
+        pa.t0 = tb;
+        pa.Tc = Tc;
+        pa.Tpad = Tpad;
+        const double rows = (double)np * Tc;
+        timed(c, GTOD_KERNEL_PANEL, rows, s, [&] { launch_panel(pa, s); });
+        ga.p0 = p0;
+        ga.n_pix = np;
+        ga.t0 = tb;
+        ga.Tc = Tc;
+        ga.Tpad = Tpad;
+        ga.n_tt = (int)((int64_t)np * Tpad / kRowPad);
+        ga.n_cg = (f.Kp + 127) / 128;
+        if (plan[i].precision == GTOD_PREC_SPLIT_BF16)
+          timed(c, GTOD_KERNEL_GEMM_BF16, rows, s, [&] { launch_gemm_bf16(ga, s); });
+        else
+          timed(c, GTOD_KERNEL_GEMM_F32, rows, s, [&] { launch_gemm_f32(ga, s); });
+      }
+    }
+  }
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipEventRecord(w->ev[slot], s));
+  w->ev_used[slot] = true;
+  return GTOD_OK;
+}
+
+gtod_status gtod_free(gtod_ctx* c, int32_t kind, int32_t id) {
+  if (!c) return GTOD_EINVAL;
+  (void)hipSetDevice(c->device);
+  if (kind == GTOD_OBJ_SCREEN) {
+    auto it = c->screens.find(id);
+    if (it == c->screens.end()) return fail(c, GTOD_ENOTFOUND, "unknown screen id");
+    HIP_TRY(c, hipDeviceSynchronize());
+    dev_free(c, it->second.pwv);
+    c->screens.erase(it);
+    return GTOD_OK;
+  }
+  if (kind == GTOD_OBJ_SPEC) {
+    auto it = c->specs.find(id);
+    if (it == c->specs.end()) return fail(c, GTOD_ENOTFOUND, "unknown spec id");
+    HIP_TRY(c, hipDeviceSynchronize());
+    free_spec(c, it->second);
+    c->specs.erase(it);
+    return GTOD_OK;
+  }
+  if (kind == GTOD_OBJ_CTX) {
+    (void)hipDeviceSynchronize();
+    drain_profile(c);
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    for (auto& kv : c->screens) dev_free(c, kv.second.pwv);
+    for (auto& kv : c->specs) free_spec(c, kv.second);
+    for (auto& kv : c->ws) free_ws(c, kv.second);
+    dev_free(c, c->counters);
+    delete c;
+    return GTOD_OK;
+  }
+  return fail(c, GTOD_EINVAL, "unknown object kind");
+}
+
+const char* gtod_last_error(const gtod_ctx* c) {
+  return c ? c->err.c_str() : g_init_err.c_str();
+}
+
+gtod_status gtod_memory(const gtod_ctx* c, uint64_t* used, uint64_t* budget) {
+  if (!c) return GTOD_EINVAL;
+  if (used) *used = c->used;
+  if (budget) *budget = c->budget;
+  return GTOD_OK;
+}
+
+gtod_status gtod_get_counters(gtod_ctx* c, uint64_t out[2]) {
+  if (!c || !out) return GTOD_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipDeviceSynchronize());
+  unsigned long long h[2];
+  HIP_TRY(c, hipMemcpy(h, c->counters, sizeof(h), hipMemcpyDeviceToHost));
+  out[0] = h[0];
+  out[1] = h[1];
+  return GTOD_OK;
+}
+
+gtod_status gtod_spec_nep2_ref(gtod_ctx* c, int32_t spec_id, double* out) {
+  if (!c || !out) return GTOD_EINVAL;
+  auto it = c->specs.find(spec_id);
+  if (it == c->specs.end()) return fail(c, GTOD_ENOTFOUND, "unknown spec id");
+  std::memcpy(out, it->second.nep2ref.data(), it->second.nep2ref.size() * 8);
+  return GTOD_OK;
+}
+
+gtod_status gtod_philox(gtod_ctx* c, const uint32_t* ctr, uint32_t* out, int64_t n,
+                        uint64_t seed, void* hip_stream) {
+  if (!c || n < 0 || (n > 0 && (!ctr || !out))) return fail(c, GTOD_EINVAL, "bad arguments");
+  if (n == 0) return GTOD_OK;
+  HIP_TRY(c, hipSetDevice(c->device));
+  launch_philox(ctr, out, n, (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32),
+                (hipStream_t)hip_stream);
+  HIP_TRY(c, hipGetLastError());
+  return GTOD_OK;
+}
+
+gtod_status gtod_profile_enable(gtod_ctx* c, int32_t enable) {
+  if (!c) return GTOD_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (enable) {
+    HIP_TRY(c, hipDeviceSynchronize());
+    drain_profile(c);
+    for (int k = 0; k < GTOD_N_KERNELS; ++k)
+      c->prof_ms[k] = c->prof_n[k] = c->prof_units[k] = 0.0;
+  }
+  c->prof = enable != 0;
+  return GTOD_OK;
+}
+
+gtod_status gtod_profile_read(gtod_ctx* c, double* out, int32_t n_kernels) {
+  if (!c || !out || n_kernels < 0) return GTOD_EINVAL;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipDeviceSynchronize());
+  drain_profile(c);
+  for (int k = 0; k < n_kernels && k < GTOD_N_KERNELS; ++k) {
+    out[3 * k] = c->prof_ms[k];
+    out[3 * k + 1] = c->prof_n[k];
+    out[3 * k + 2] = c->prof_units[k];
+  }
+  return GTOD_OK;
+}
+
+void gtod_abi_sizes(int64_t out[5]) {
+  out[0] = sizeof(gtod_init_desc);
+  out[1] = sizeof(gtod_screen_desc);
+  out[2] = sizeof(gtod_stage);
+  out[3] = sizeof(gtod_spectral_desc);
+  out[4] = sizeof(gtod_job);
+}
+
+}  // extern "C"

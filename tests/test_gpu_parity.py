@@ -1,0 +1,239 @@
+"""GPU (HIP) path against the FP64 oracle, through the C-ABI.
+
+Tolerances (stated for the FP32 path): noise-free P_KID and the TOD within
+1e-6 relative of the oracle, element by element; photon-noise sigma within
+1e-5 relative; the 1/f series within 1e-5 of its rms; Philox words
+bit-exact.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2604_23305_amd as g
+from oracle import philox as op
+from oracle import pink as opk
+from tests.gpu_util import new_ctx, rel_err, report, run_signal
+from tests.test_oracle_pins import tiny_scenario
+from workloads import configs
+
+pytestmark = pytest.mark.gpu
+
+TOL_PKID = 1e-6
+TOL_SIGMA = 1e-5
+TOL_PINK = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = new_ctx()
+    yield c
+    g.free(c)
+
+
+def test_philox_words_bit_exact(ctx):
+    rng = np.random.default_rng(0)
+    n = 4096
+    ctr = rng.integers(0, 2**32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[:16] = 0
+    ctr[16:32, 0] = np.arange(16)
+    for seed in (0, 1, 0x123456789ABCDEF, 2**64 - 1):
+        d_ctr = torch.from_numpy(ctr.view(np.int32)).cuda()
+        d_out = torch.zeros((n, 4), dtype=torch.int32, device="cuda")
+        g.philox(ctx, d_ctr, d_out, n, seed)
+        torch.cuda.synchronize()
+        got = d_out.cpu().numpy().view(np.uint32)
+        ref = np.stack(op.philox4x32_10(ctr[:, 0], ctr[:, 1], ctr[:, 2],
+                                        ctr[:, 3], op.key_of(seed)), axis=1)
+        np.testing.assert_array_equal(got, ref)
+
+
+def _compare(sc, out, ref, tol_pk=TOL_PKID, t_slice=slice(None)):
+    pk = out.p_kid.cpu().numpy()[..., t_slice]
+    e_pk = rel_err(pk, ref["p_kid"])
+    report("p_kid", e_pk)
+    e_sg = rel_err(out.sigma.cpu().numpy()[..., t_slice], ref["sigma"])
+    report("sigma", e_sg)
+    e_tod = rel_err(out.tod.cpu().numpy()[..., t_slice], ref["tod"])
+    report("tod", e_tod)
+    assert e_pk.max() <= tol_pk
+    assert e_sg.max() <= TOL_SIGMA
+    assert e_tod.max() <= tol_pk
+
+
+@pytest.mark.parametrize("noise", [False, True])
+def test_c1_full_parity(ctx, noise):
+    sc = configs.c1(noise=noise)
+    ref = oracle.tod.simulate(sc)
+    _, out = run_signal(ctx, sc, with_pwv=True)
+    _compare(sc, out, ref)
+    np.testing.assert_allclose(out.pwv.cpu().numpy(), ref["pwv"], rtol=1e-7)
+
+
+@pytest.mark.parametrize("filt", ["filterbank", "lorentz", "matrix"])
+@pytest.mark.parametrize("shape", [(8, 3, 2, 5), (37, 33, 3, 131),
+                                   (100, 130, 2, 300)])
+def test_tiny_and_ragged_shapes(ctx, filt, shape):
+    """Shapes that leave ragged F, K and T tiles; every cascade kind."""
+    F, K, P, T = shape
+    sc = tiny_scenario(F=F, K=K, P=P, T=T, filt=filt,
+                       stages=configs.cascade_table2())
+    ref = oracle.tod.simulate(sc)
+    _, out = run_signal(ctx, sc)
+    _compare(sc, out, ref)
+
+
+def test_window_of_rows_only(ctx):
+    """t_begin/t_end select rows; the rest of tod stays untouched."""
+    sc = configs.c1()
+    ref = oracle.tod.simulate(sc, 300, 777)
+    run, out = run_signal(ctx, sc, 300, 777)
+    pk = out.p_kid.cpu().numpy()
+    assert np.all(pk[..., :300] == 0) and np.all(pk[..., 777:] == 0)
+    _compare(sc, out, ref, t_slice=slice(300, 777))
+
+
+def test_accumulate_adds_into_tod(ctx):
+    sc = configs.c1(noise=False)
+    run = g.ScenarioRun(ctx, sc)
+    out = run.alloc(with_p_kid=True)
+    out.tod.fill_(1.0e-12)
+    g.simulate_tod(ctx, [run.signal_job(out, accumulate=True)])
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(out.tod.cpu().numpy(),
+                               out.p_kid.cpu().numpy().astype(np.float64) + 1e-12,
+                               rtol=1e-6)
+
+
+def test_uniform_screen_gives_constant_tod(ctx):
+    sc = configs.c1(noise=False, uniform_screen=True)
+    _, out = run_signal(ctx, sc)
+    pk = out.p_kid.cpu().numpy().astype(np.float64)
+    spread = np.ptp(pk, axis=-1) / pk.mean(axis=-1)
+    assert spread.max() <= 2e-7
+
+
+def test_chunking_is_invisible(ctx):
+    """A small workspace forces many chunks: outputs are bit-identical."""
+    sc = configs.c1()
+    _, out_a = run_signal(ctx, sc)
+    small = new_ctx(workspace_bytes=8 << 20)
+    try:
+        _, out_b = run_signal(small, sc)
+        assert torch.equal(out_a.tod, out_b.tod)
+        assert torch.equal(out_a.sigma, out_b.sigma)
+    finally:
+        g.free(small)
+
+
+def test_pink_series_match_oracle(ctx):
+    sc = configs.c1()
+    run = g.ScenarioRun(ctx, sc)
+    tod = torch.zeros((sc.n_pix, sc.K, sc.t_total), device="cuda")
+    g.simulate_tod(ctx, [run.pink_job(tod, accumulate=False)])
+    torch.cuda.synchronize()
+    got = tod.cpu().numpy()
+    nep2 = oracle.tod.reference_nep2(sc)
+    A = opk.amplitude(nep2, sc.pink_alpha, sc.pink_knee_hz)
+    for k in (0, 1, 17, 63):
+        ref = opk.series(sc.seed, 0, k, A[k], sc.pink_alpha[k], sc.t_total,
+                         sc.f_sample_hz)
+        err = np.abs(got[0, k] - ref).max() / ref.std()
+        print(f"  pink k={k}: max err / rms {err:.3e}", flush=True)
+        assert err <= TOL_PINK
+
+
+@pytest.mark.parametrize("T", [1, 2, 3, 100, 4097, 9000])
+def test_pink_lengths(ctx, T):
+    """Lengths around powers of two, down to a single sample; includes the
+    two-pass transform (T > 8192)."""
+    sc = tiny_scenario(F=16, K=3, P=2, T=T)
+    sc.pink_alpha = np.array([1.0, 0.5, 2.0])
+    run = g.ScenarioRun(ctx, sc)
+    tod = torch.zeros((sc.n_pix, sc.K, T), device="cuda")
+    g.simulate_tod(ctx, [run.pink_job(tod, accumulate=False)])
+    torch.cuda.synchronize()
+    got = tod.cpu().numpy()
+    nep2 = oracle.tod.reference_nep2(sc)
+    A = opk.amplitude(nep2, sc.pink_alpha, 1.0)
+    for p in range(2):
+        for k in range(3):
+            ref = opk.series(sc.seed, p, k, A[k], sc.pink_alpha[k], T, 160.0)
+            if T <= 2:
+                assert np.all(got[p, k] == 0) and np.all(ref == 0)
+                continue
+            err = np.abs(got[p, k] - ref).max() / ref.std()
+            assert err <= TOL_PINK, (p, k, err)
+
+
+def test_nep2_reference_matches_oracle(ctx):
+    sc = configs.c2(t_total=256, screen_shape=(64, 4096))
+    run = g.ScenarioRun(ctx, sc)
+    got = g.spec_nep2_ref(ctx, run.spec_id, sc.K)
+    ref = oracle.tod.reference_nep2(sc)
+    assert np.max(np.abs(got / ref - 1)) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", [g.PREC_FP32, g.PREC_SPLIT_BF16])
+def test_c2_full_run_windows(ctx, prec):
+    """Single-pixel spectrometer at full size (raster, 96k samples): the
+    whole run on the GPU, three 2048-sample windows against the oracle."""
+    sc = configs.c2()
+    run, out = run_signal(ctx, sc, precision=prec)
+    T = sc.t_total
+    for a in (0, T // 2 - 1024, T - 2048):
+        ref = oracle.tod.simulate(sc, a, a + 2048)
+        print(f" window {a}", flush=True)
+        _compare(sc, out, ref, t_slice=slice(a, a + 2048))
+
+
+def test_split_matches_fp32_closely(ctx):
+    sc = configs.c1(noise=False)
+    _, o32 = run_signal(ctx, sc, precision=g.PREC_FP32)
+    _, obf = run_signal(ctx, sc, precision=g.PREC_SPLIT_BF16)
+    d = rel_err(obf.p_kid.cpu().numpy(), o32.p_kid.cpu().numpy().astype(np.float64))
+    report("split vs fp32", d)
+    assert d.max() <= 1e-6
+
+
+def test_error_paths(ctx):
+    sc = configs.c1()
+    run = g.ScenarioRun(ctx, sc)
+    out = run.alloc()
+    job = run.signal_job(out)
+    bad = run.signal_job(out)
+    bad.spec_id = 999
+    with pytest.raises(g.GtodError, match="ENOTFOUND"):
+        g.simulate_tod(ctx, [job, bad])
+    bad = run.signal_job(out, 0, sc.t_total)
+    bad.t_end = sc.t_total + 1
+    with pytest.raises(g.GtodError, match="EINVAL"):
+        g.simulate_tod(ctx, [bad])
+    bad = run.signal_job(out)
+    bad.n_az = 1
+    with pytest.raises(g.GtodError, match="EINVAL"):
+        g.simulate_tod(ctx, [bad])
+    with pytest.raises(g.GtodError, match="ENOTFOUND"):
+        g.free(ctx, g.OBJ_SCREEN, 12345)
+    tiny = new_ctx(hbm_budget_bytes=64 << 20, workspace_bytes=1 << 30)
+    try:
+        r2 = g.ScenarioRun(tiny, sc)
+        o2 = r2.alloc()
+        with pytest.raises(g.GtodError, match="EBUDGET"):
+            g.simulate_tod(tiny, [r2.signal_job(o2)])
+    finally:
+        g.free(tiny)
+
+
+def test_strict_range_rejects_leaving_screen():
+    sc = configs.c1()
+    c = new_ctx(strict_range=True)
+    try:
+        run = g.ScenarioRun(c, sc)
+        out = run.alloc()
+        sc.dtheta[0] = 0.05   # 77 m off a 12.8 m-wide screen
+        run.dtheta[0] = 0.05
+        with pytest.raises(g.GtodError, match="ERANGE"):
+            g.simulate_tod(c, [run.signal_job(out)])
+    finally:
+        g.free(c)
