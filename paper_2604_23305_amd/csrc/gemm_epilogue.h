@@ -1,5 +1,7 @@
 // Epilogue shared by the contraction kernels: reference terms, photon-noise
 // sigma, Philox white noise and the store into [pixel][channel][time].
+// Accumulators are in panel units (powers times 2^p); C2 holds dP^2 and
+// carries 2^2p.
 //
 // Each wave owns 2 x 2 accumulator tiles of 32 channels x 32 samples (3
 // products).  A tile is first written to the wave's slice of LDS with
@@ -36,7 +38,7 @@ __device__ __forceinline__ void contraction_epilogue(
       for (int e = 0; e < 16; ++e) {
         const int chl = 8 * (e >> 2) + 4 * h + (e & 3);
         spk[chl * kEpiPitch + c] = acc[0][i][j][e];
-        sn2[chl * kEpiPitch + c] = acc[1][i][j][e] + acc[2][i][j][e];
+        sn2[chl * kEpiPitch + c] = acc[1][i][j][e] + acc[2][i][j][e] * a.pinv_f;
       }
       __syncthreads();
       if (!live[i]) continue;
@@ -51,9 +53,11 @@ __device__ __forceinline__ void contraction_epilogue(
         const int chl = 2 * s + h;
         const int ch = chb + chl;
         if (ch >= a.K) break;
-        const float pk = (float)a.c0[ch] + spk[chl * kEpiPitch + c];
-        const float n2 = (float)a.c1[ch] + sn2[chl * kEpiPitch + c];
-        const float sg = sqrtf(fmaxf(n2, 0.f) * a.fs_half);
+        // P_KID = c0 + C0 2^-p; NEP^2 = c1 + (C1 + C2 2^-p) 2^-p, in FP64
+        // because 2^-2p lies below the FP32 normal range
+        const float pk = (float)(a.c0[ch] + (double)spk[chl * kEpiPitch + c] * a.pinv);
+        const double n2 = a.c1[ch] + (double)sn2[chl * kEpiPitch + c] * a.pinv;
+        const float sg = (float)sqrt(fmax(n2, 0.0) * (double)a.fs_half);
         float v = pk;
         if (a.photon) {
           const u32x4 o = philox10(u32x4{(uint32_t)t, (uint32_t)ch, (uint32_t)p, 0u},

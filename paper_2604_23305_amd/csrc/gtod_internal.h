@@ -63,6 +63,11 @@ struct GemmArgs {
   int p0, n_pix, Tc, Tpad;
   int64_t t0, t_total;
   float fs_half;
+  // The panel carries spectral powers times 2^pexp (power-of-two scale,
+  // exact) so that dP and dP^2 stay in the normal FP32 range; the
+  // epilogue multiplies by pinv = 2^-pexp.
+  double pinv;
+  float pinv_f;
   uint32_t key0, key1;
   int photon, accumulate;
   float* tod;
@@ -126,6 +131,8 @@ struct PassTable {
 
 void launch_spec_setup(const SpecSetupArgs& a, const PassTable& pt,
                        hipStream_t s);
+void launch_scale_spectra(float* E, float* D, float* W, float* Pref, int Fp,
+                          float scale, hipStream_t s);
 void launch_panel(const PanelArgs& a, hipStream_t s);
 void launch_gemm_f32(const GemmArgs& a, hipStream_t s);
 void launch_gemm_bf16(const GemmArgs& a, hipStream_t s);

@@ -194,6 +194,22 @@ __global__ __launch_bounds__(256) void k_reference(SpecSetupArgs a) {
   }
 }
 
+__global__ void k_scale_spectra(float* E, float* D, float* W, float* Pref,
+                                int Fp, float scale) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= Fp) return;
+  E[j] *= scale;
+  D[j] *= scale;
+  W[j] *= scale;
+  Pref[j] *= scale;
+}
+
+void launch_scale_spectra(float* E, float* D, float* W, float* Pref, int Fp,
+                          float scale, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_spectra, dim3((Fp + 127) / 128), dim3(128), 0, s,
+                     E, D, W, Pref, Fp, scale);
+}
+
 void launch_spec_setup(const SpecSetupArgs& a, const PassTable& pt,
                        hipStream_t s) {
   const int bs = 128;

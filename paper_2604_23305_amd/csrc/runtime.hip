@@ -40,6 +40,7 @@ struct SpecObj {
   uint16_t* Bl = nullptr;
   double* c0 = nullptr;
   double* c1 = nullptr;
+  int pexp = 0;   // the panel carries spectral powers times 2^pexp
   std::vector<double> nep2ref;
   std::vector<void*> allocs;
 };
@@ -615,6 +616,21 @@ gtod_status gtod_load_filters(gtod_ctx* c, const gtod_spectral_desc* d, int32_t*
     so.nep2ref.resize(K);
     e = hipMemcpy(so.nep2ref.data(), so.c1, K * 8, hipMemcpyDeviceToHost);
   }
+  if (e == hipSuccess) {
+    // power-of-two scale bringing the largest reference power to [1, 2)
+    std::vector<double> pref(Fp);
+    e = hipMemcpy(pref.data(), d_pref64, Fp * 8, hipMemcpyDeviceToHost);
+    double mx = 0.0;
+    for (double v : pref) mx = std::max(mx, std::fabs(v));
+    so.pexp = (mx > 0.0 && std::isfinite(mx)) ? -std::ilogb(mx) : 0;
+    so.pexp = std::max(-60, std::min(so.pexp, 100));
+    if (e == hipSuccess) {
+      launch_scale_spectra(so.E, so.D, so.W, so.Pref, so.Fp,
+                           std::ldexp(1.0f, so.pexp), nullptr);
+      e = hipGetLastError();
+      if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+  }
   cleanup();
   if (e != hipSuccess) {
     free_spec(c, so);
@@ -794,6 +810,8 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
     ga.Kp = f.Kp;
     ga.t_total = j.t_total;
     ga.fs_half = (float)(0.5 * c->fs);
+    ga.pinv = std::ldexp(1.0, -f.pexp);
+    ga.pinv_f = std::ldexp(1.0f, -f.pexp);
     ga.key0 = key0;
     ga.key1 = key1;
     ga.photon = (j.flags & GTOD_JOB_PHOTON_NOISE) != 0;
