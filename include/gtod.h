@@ -226,10 +226,14 @@ gtod_status gtod_load_filters(gtod_ctx* ctx, const gtod_spectral_desc* desc,
  *   the 1/f spectrum of series (p, k) uses counter (j, k, p, 1).
  *   PINK: PSD A_k f^-alpha_k with A_k = NEP^2_ref,k * pink_knee_hz^alpha_k
  *   (pink_alpha host [K]).
- * Outputs (device, caller-owned; layout [n_pix][K][t_total], time fastest):
+ * Outputs (device, caller-owned; layout [n_pix][K][out_ld], time fastest,
+ *   holding samples [out_t0, out_t0 + out_ld); out_ld = 0 means out_t0 = 0
+ *   and out_ld = t_total):
  *   tod (required): power (+ noise) in W.  p_kid, sigma (optional, SIGNAL):
  *   noise-free power and photon-noise sigma.  pwv (optional, SIGNAL):
- *   [n_pix][t_total] zenith PWV sampled at each row.
+ *   [n_pix][out_ld] zenith PWV sampled at each row.
+ *   SIGNAL needs out_t0 <= t_begin and t_end <= out_t0 + out_ld; PINK
+ *   needs out_t0 = 0 and out_ld >= t_total.
  */
 typedef struct gtod_job {
   int32_t kind;
@@ -253,6 +257,7 @@ typedef struct gtod_job {
   int32_t reserved0;
   const double* pink_alpha;
   double pink_knee_hz;
+  int64_t out_t0, out_ld;
   float* tod;
   float* p_kid;
   float* sigma;

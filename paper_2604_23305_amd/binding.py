@@ -215,6 +215,8 @@ class Outputs:
     p_kid: object = None
     sigma: object = None
     pwv: object = None
+    t0: int = 0            # first sample held
+    length: int = 0        # samples held per (pixel, channel)
 
 
 class ScenarioRun:
@@ -247,14 +249,17 @@ class ScenarioRun:
         self.alpha = (None if sc.pink_alpha is None else _f64(sc.pink_alpha))
 
     def alloc(self, with_p_kid=False, with_sigma=False, with_pwv=False,
-              device="cuda"):
+              device="cuda", t0=0, length=None):
+        """Output buffers for samples [t0, t0 + length) (default: all)."""
         import torch
         sc = self.sc
-        shape = (sc.n_pix, sc.K, sc.t_total)
+        length = sc.t_total if length is None else length
+        shape = (sc.n_pix, sc.K, length)
         z = lambda s: torch.zeros(s, dtype=torch.float32, device=device)
         return Outputs(tod=z(shape), p_kid=z(shape) if with_p_kid else None,
                        sigma=z(shape) if with_sigma else None,
-                       pwv=z((sc.n_pix, sc.t_total)) if with_pwv else None)
+                       pwv=z((sc.n_pix, length)) if with_pwv else None,
+                       t0=t0, length=length)
 
     def signal_job(self, out: Outputs, t_begin=0, t_end=None, precision=-1,
                    photon_noise=None, accumulate=False) -> _abi.Job:
@@ -273,6 +278,7 @@ class ScenarioRun:
                      seed=sc.seed,
                      flags=(JOB_PHOTON_NOISE if noise else 0)
                      | (JOB_ACCUMULATE if accumulate else 0),
+                     out_t0=out.t0, out_ld=out.length,
                      tod=out.tod.data_ptr(),
                      p_kid=out.p_kid.data_ptr() if out.p_kid is not None else None,
                      sigma=out.sigma.data_ptr() if out.sigma is not None else None,

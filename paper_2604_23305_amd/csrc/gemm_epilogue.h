@@ -66,7 +66,7 @@ __device__ __forceinline__ void contraction_epilogue(
           box_muller(o.x, o.y, &zc, &zs);
           v += sg * zc;
         }
-        const int64_t off = ((int64_t)p * a.K + ch) * a.t_total + t;
+        const int64_t off = ((int64_t)p * a.K + ch) * a.out_ld + (t - a.out_t0);
         if (a.accumulate) a.tod[off] += v; else a.tod[off] = v;
         if (a.p_kid) a.p_kid[off] = pk;
         if (a.sigma) a.sigma[off] = sg;

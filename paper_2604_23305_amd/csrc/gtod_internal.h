@@ -47,8 +47,8 @@ struct PanelArgs {
   int64_t t0;
   int Tc, Tpad;
   float* panel;          // [n_pix*Tpad][Fp]
-  float* pwv_out;        // [n_pix_job][t_total] or null
-  int64_t t_total;
+  float* pwv_out;        // [n_pix_job][out_ld] or null
+  int64_t out_t0, out_ld;
   unsigned long long* counters;  // [2]
 };
 
@@ -61,7 +61,7 @@ struct GemmArgs {
   const double* c1;      // [Kp] reference NEP^2
   int Fp, K, Kp;
   int p0, n_pix, Tc, Tpad;
-  int64_t t0, t_total;
+  int64_t t0, out_t0, out_ld;
   float fs_half;
   // The panel carries spectral powers times 2^pexp (power-of-two scale,
   // exact) so that dP and dP^2 stay in the normal FP32 range; the
@@ -87,7 +87,7 @@ struct PinkArgs {
   const float* alpha;    // [K]
   uint32_t key0, key1;
   float* tod;
-  int64_t t_total;
+  int64_t t_total, out_ld;
   int accumulate;
   int B2;
 };

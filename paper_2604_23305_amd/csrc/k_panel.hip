@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
       const double pwv = (1.0 - wx) * (1.0 - wy) * s0[0] + wx * (1.0 - wy) * s0[1] +
                          (1.0 - wx) * wy * s0[a.nx] + wx * wy * s0[a.nx + 1];
       if (ox || oy) atomicAdd(&a.counters[0], 1ull);
-      if (a.pwv_out) a.pwv_out[(int64_t)p * a.t_total + n] = (float)pwv;
+      if (a.pwv_out) a.pwv_out[(int64_t)p * a.out_ld + (n - a.out_t0)] = (float)pwv;
       int64_t li;
       double lw;
       bool ol;

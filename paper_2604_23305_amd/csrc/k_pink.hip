@@ -85,7 +85,7 @@ __device__ __forceinline__ float2 spectrum_bin(const PinkArgs& a, int64_t j,
 __device__ __forceinline__ void store_out(const PinkArgs& a, int64_t series,
                                           int64_t m, float2 z) {
   const int64_t t = 2 * m;
-  float* dst = a.tod + series * a.t_total;
+  float* dst = a.tod + series * a.out_ld;
   if (t < a.t_total) {
     if (a.accumulate) dst[t] += z.x; else dst[t] = z.x;
   }

@@ -249,6 +249,12 @@ gtod_status validate(gtod_ctx* c, const gtod_job& j, int idx, JobPlan* pl) {
     return fail(c, GTOD_EINVAL, at + "t_total out of range");
   if (j.flags & ~(GTOD_JOB_PHOTON_NOISE | GTOD_JOB_ACCUMULATE))
     return fail(c, GTOD_EINVAL, at + "unknown flags");
+  const int64_t ot0 = j.out_ld ? j.out_t0 : 0, old = j.out_ld ? j.out_ld : j.t_total;
+  if (old < 1 || ot0 < 0) return fail(c, GTOD_EINVAL, at + "bad output window");
+  if (j.kind == GTOD_JOB_PINK && (ot0 != 0 || old < j.t_total))
+    return fail(c, GTOD_EINVAL, at + "PINK output must hold all t_total samples");
+  if (j.kind == GTOD_JOB_SIGNAL && (j.t_begin < ot0 || j.t_end > ot0 + old))
+    return fail(c, GTOD_EINVAL, at + "output window does not cover [t_begin, t_end)");
   const int prec = j.precision < 0 ? c->precision : j.precision;
   if (prec != GTOD_PREC_FP32 && prec != GTOD_PREC_SPLIT_BF16)
     return fail(c, GTOD_EINVAL, at + "unknown precision");
@@ -724,6 +730,7 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
       a.key1 = key1;
       a.tod = j.tod;
       a.t_total = j.t_total;
+      a.out_ld = j.out_ld ? j.out_ld : j.t_total;
       a.accumulate = acc;
       a.scratch = w->pink;
       const int64_t S = (int64_t)j.n_pix * f.K;
@@ -796,7 +803,8 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
     pa.del = j.del_rad;
     pa.panel = w->panel;
     pa.pwv_out = j.pwv;
-    pa.t_total = j.t_total;
+    pa.out_t0 = j.out_ld ? j.out_t0 : 0;
+    pa.out_ld = j.out_ld ? j.out_ld : j.t_total;
     pa.counters = c->counters;
     GemmArgs ga{};
     ga.panel = w->panel;
@@ -808,7 +816,8 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
     ga.Fp = f.Fp;
     ga.K = f.K;
     ga.Kp = f.Kp;
-    ga.t_total = j.t_total;
+    ga.out_t0 = pa.out_t0;
+    ga.out_ld = pa.out_ld;
     ga.fs_half = (float)(0.5 * c->fs);
     ga.pinv = std::ldexp(1.0, -f.pexp);
     ga.pinv_f = std::ldexp(1.0f, -f.pexp);
