@@ -314,9 +314,11 @@ gtod_status gtod_philox(gtod_ctx* ctx, const uint32_t* ctr, uint32_t* out,
  * HIP events recorded on its launch stream.  gtod_profile_enable(ctx, 1)
  * clears the totals and starts; 0 stops.  gtod_profile_read synchronises
  * the device and writes, for each kernel id k < n_kernels,
- * out[3k] = total milliseconds, out[3k+1] = launches, out[3k+2] = work
- * units (rows for the panel and contraction kernels, complex points for
- * the two 1/f passes). */
+ * out[3k] = total milliseconds, out[3k+1] = launches, out[3k+2] =
+ * algorithmic work: for the panel, bytes (20F + 32 per row: four source
+ * spectra, the deviation row, four screen values); for the contractions,
+ * FLOP (6 K F per row: three products); for the 1/f passes, complex
+ * points. */
 #define GTOD_KERNEL_PANEL 0
 #define GTOD_KERNEL_GEMM_F32 1
 #define GTOD_KERNEL_GEMM_BF16 2

@@ -223,7 +223,8 @@ class ScenarioRun:
     """Loads a scenario's screen and spectral setup into a context, keeps
     its source cube and trajectory on the device, and builds jobs."""
 
-    def __init__(self, ctx, sc, device="cuda", screen_id=None, spec_id=None):
+    def __init__(self, ctx, sc, device="cuda", screen_id=None, spec_id=None,
+                 cube=None):
         import torch
         self.ctx = ctx
         self.sc = sc
@@ -237,8 +238,8 @@ class ScenarioRun:
             ctx, sp.nu_hz, sp.w_hz, sp.eta_z, sp.pwv0_mm, sp.dpwv_mm,
             sp.t_atm_K, sp.stages, fil.mode, fil.f_hz, fil.R, fil.eta_peak,
             fil.matrix, sp.ref_pwv_mm, sp.ref_el_rad)
-        self.cube = None
-        if sc.source is not None:
+        self.cube = cube
+        if cube is None and sc.source is not None:
             self.cube = torch.from_numpy(np.ascontiguousarray(
                 sc.source.cube, dtype=np.float32)).to(device)
         self.traj = None

@@ -839,7 +839,9 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
         pa.Tc = Tc;
         pa.Tpad = Tpad;
         const double rows = (double)np * Tc;
-        timed(c, GTOD_KERNEL_PANEL, rows, s, [&] { launch_panel(pa, s); });
+        timed(c, GTOD_KERNEL_PANEL, rows * (20.0 * f.F + 32.0), s,
+              [&] { launch_panel(pa, s); });
+        const double flop = rows * 6.0 * f.K * f.F;
         ga.p0 = p0;
         ga.n_pix = np;
         ga.t0 = tb;
@@ -848,9 +850,9 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
         ga.n_tt = (int)((int64_t)np * Tpad / kRowPad);
         ga.n_cg = (f.Kp + 127) / 128;
         if (plan[i].precision == GTOD_PREC_SPLIT_BF16)
-          timed(c, GTOD_KERNEL_GEMM_BF16, rows, s, [&] { launch_gemm_bf16(ga, s); });
+          timed(c, GTOD_KERNEL_GEMM_BF16, flop, s, [&] { launch_gemm_bf16(ga, s); });
         else
-          timed(c, GTOD_KERNEL_GEMM_F32, rows, s, [&] { launch_gemm_f32(ga, s); });
+          timed(c, GTOD_KERNEL_GEMM_F32, flop, s, [&] { launch_gemm_f32(ga, s); });
       }
     }
   }

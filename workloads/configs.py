@@ -157,3 +157,55 @@ def c3(t_total=576000, screen_shape=(1024, 262144), n_side=7, noise=True,
 def c4(**kw):
     kw.setdefault("faint", True)
     return c3(name="c4", seed=4, **kw)
+
+
+# --------------------------------------------------------------------------
+# c5: serving stream
+# --------------------------------------------------------------------------
+def c5_spectral(K, F):
+    """Spectral setup of a serving request: K-channel filterbank (R=500,
+    eta_peak 0.16) over 220-440 GHz, F bins, Table-1-shaped cascade."""
+    return spectral(F, lorentz_bank(K, eta_peak=0.16, mode="filterbank"),
+                    cascade_c2())
+
+
+def c5_screens(n=4, shape=(512, 65536)):
+    return [screen(*shape, 50 + i) for i in range(n)]
+
+
+def c5_pixels(n_pix):
+    if n_pix == 49:
+        return gen.square_spaxels(7, 12 * ARCSEC)
+    r = {1: 0, 7: 1, 19: 2}[n_pix]
+    return gen.hex_spaxels(r, 12 * ARCSEC)
+
+
+def c5_requests(n=256, rate_hz=20.0, seed=5, **kw):
+    """Request parameters (arrival, pixels, channels, bins, duration,
+    screen, seed); samples = round(duration * 160 Hz)."""
+    reqs = gen.request_stream(n, rate_hz, seed, **kw)
+    for r in reqs:
+        r["t_total"] = int(round(r["duration_s"] * F_SAMPLE))
+    return reqs
+
+
+def c5_scenario(req, screens, spectral_cache=None, source_cache=None):
+    """Scenario of one serving request (daisy scan, c2-style line source on
+    a 55x55 grid over +-70 arcsec).  Caches let requests share setups."""
+    K, F = req["K"], req["F"]
+    sp = spectral_cache.get((K, F)) if spectral_cache is not None else None
+    if sp is None:
+        sp = c5_spectral(K, F)
+        if spectral_cache is not None:
+            spectral_cache[(K, F)] = sp
+    src = source_cache.get(F) if source_cache is not None else None
+    if src is None:
+        src = line_source(sp.nu_hz)
+        if source_cache is not None:
+            source_cache[F] = src
+    dphi, dth = c5_pixels(req["n_pix"])
+    return Scenario(
+        name=f"c5-r{req['rid']}", f_sample_hz=F_SAMPLE, spectral=sp,
+        screen=screens[req["screen"]], scan=daisy_scan(), dphi=dphi,
+        dtheta=dth, t_total=req["t_total"], source=src, seed=req["seed"],
+        photon_noise=True, pink_alpha=np.ones(K), pink_knee_hz=1.0)
