@@ -74,6 +74,29 @@ class Request:
     def out_bytes(self) -> int:
         return self.det_samples * 4
 
+    @staticmethod
+    def from_run(run, rid, arrival_s, precision=-1) -> "Request":
+        """Request for a binding.ScenarioRun (resident screen, spectral
+        setup and source cube)."""
+        sc = run.sc
+        cube_grid = (0, 0, 0, 0.0, 0.0, 0.0, 0.0)
+        if sc.source is not None:
+            s = sc.source
+            cube_grid = (s.n_az, s.n_el, s.cube.shape[2], s.az0, s.daz,
+                         s.el0, s.del_)
+        kind = {"stare": _abi.SCAN_STARE, "daisy": _abi.SCAN_DAISY}[
+            sc.scan.kind]
+        return Request(rid=rid, arrival_s=arrival_s, spec_id=run.spec_id,
+                       screen_id=run.screen_id, K=sc.K, n_pix=sc.n_pix,
+                       dphi=run.dphi, dtheta=run.dtheta, t_total=sc.t_total,
+                       seed=sc.seed, scan_kind=kind,
+                       scan_params=(sc.scan.r_petal, sc.scan.omega,
+                                    sc.scan.Omega),
+                       phi0=sc.scan.phi0, theta0=sc.scan.theta0,
+                       cube=run.cube, cube_grid=cube_grid,
+                       pink_alpha=run.alpha, pink_knee_hz=sc.pink_knee_hz,
+                       photon_noise=sc.photon_noise, precision=precision)
+
 
 @dataclass
 class EngineStats:
@@ -147,29 +170,6 @@ class Engine:
                         t_total=r.t_total, seed=r.seed, flags=0,
                         pink_alpha=r.pink_alpha.ctypes.data,
                         pink_knee_hz=r.pink_knee_hz, tod=r.tod.data_ptr())
-
-    @staticmethod
-    def from_run(run, rid, arrival_s, precision=-1) -> "Request":
-        """Request for a binding.ScenarioRun (resident screen, spectral
-        setup and source cube)."""
-        sc = run.sc
-        cube_grid = (0, 0, 0, 0.0, 0.0, 0.0, 0.0)
-        if sc.source is not None:
-            s = sc.source
-            cube_grid = (s.n_az, s.n_el, s.cube.shape[2], s.az0, s.daz,
-                         s.el0, s.del_)
-        kind = {"stare": _abi.SCAN_STARE, "daisy": _abi.SCAN_DAISY}[
-            sc.scan.kind]
-        return Request(rid=rid, arrival_s=arrival_s, spec_id=run.spec_id,
-                       screen_id=run.screen_id, K=sc.K, n_pix=sc.n_pix,
-                       dphi=run.dphi, dtheta=run.dtheta, t_total=sc.t_total,
-                       seed=sc.seed, scan_kind=kind,
-                       scan_params=(sc.scan.r_petal, sc.scan.omega,
-                                    sc.scan.Omega),
-                       phi0=sc.scan.phi0, theta0=sc.scan.theta0,
-                       cube=run.cube, cube_grid=cube_grid,
-                       pink_alpha=run.alpha, pink_knee_hz=sc.pink_knee_hz,
-                       photon_noise=sc.photon_noise, precision=precision)
 
     def _now(self) -> float:
         return time.perf_counter() - self._t0_wall
