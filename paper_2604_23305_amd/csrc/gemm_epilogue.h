@@ -3,8 +3,9 @@
 // Accumulators are in panel units (powers times 2^p); C2 holds dP^2 and
 // carries 2^2p.
 //
-// Each wave owns 2 x 2 accumulator tiles of 32 channels x 32 samples (3
-// products).  A tile is first written to the wave's slice of LDS with
+// Each wave owns NI x NJ accumulator tiles of 32 channels x 32 samples (3
+// products); tile (i, j) starts at channel ch_base + 32 i and row
+// row_base + 32 j.  A tile is first written to the wave's slice of LDS with
 // static register indices, then read back by a compact loop in which lane
 // l handles sample (l mod 32) of channel rows 2s + l/32: stores are runs of
 // 32 consecutive samples.
@@ -22,17 +23,18 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kEpiPitch = 33;
 constexpr int kEpiWaveFloats = 2 * 32 * kEpiPitch;
 
+template <int NI, int NJ>
 __device__ __forceinline__ void contraction_epilogue(
-    const GemmArgs& a, f32x16 (&acc)[3][2][2], float* smem, int64_t row0,
-    int ch0, int wt, int wc, const bool (&live)[2]) {
+    const GemmArgs& a, f32x16 (&acc)[3][NI][NJ], float* smem,
+    int64_t row_base, int ch_base, const bool (&live)[NI]) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int h = lane >> 5, c = lane & 31;
   float* spk = smem + wave * kEpiWaveFloats;
   float* sn2 = spk + 32 * kEpiPitch;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
+  for (int i = 0; i < NI; ++i) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < NJ; ++j) {
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
@@ -42,13 +44,13 @@ __device__ __forceinline__ void contraction_epilogue(
       }
       __syncthreads();
       if (!live[i]) continue;
-      const int64_t row = row0 + wt * 64 + j * 32 + c;
+      const int64_t row = row_base + j * 32 + c;
       const int pl = (int)(row / a.Tpad);
       const int tl = (int)(row % a.Tpad);
       if (pl >= a.n_pix || tl >= a.Tc) continue;
       const int p = a.p0 + pl;
       const int64_t t = a.t0 + tl;
-      const int chb = ch0 + wc * 64 + i * 32;
+      const int chb = ch_base + i * 32;
       for (int s = 0; s < 16; ++s) {
         const int chl = 2 * s + h;
         const int ch = chb + chl;

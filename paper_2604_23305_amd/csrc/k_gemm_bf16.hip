@@ -164,7 +164,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
     }
   }
 
-  contraction_epilogue(a, acc, smem, row0, ch0, wt, wc, live);
+  contraction_epilogue<2, 2>(a, acc, smem, row0 + wt * 64, ch0 + wc * 64, live);
 }
 
 void launch_gemm_bf16(const GemmArgs& a, hipStream_t s) {

@@ -12,8 +12,9 @@
 // Epilogue: P_KID = c0 + C0, NEP^2 = c1 + C1 + C2, sigma = sqrt(NEP^2 f/2),
 // P_wn = sigma z with z from Philox counter (t, k, p, 0).
 //
-// Workgroup: 4 waves as 2 (time) x 2 (channel), each 64 x 64 = 2 x 2 MFMA
-// tiles per product.  Operands are staged through LDS in depth chunks of
+// Workgroup: 4 waves along time, each 32 samples x all (up to 4) live
+// 32-channel tiles of the group, so a partly filled last group costs in
+// proportion to its live tiles.  Operands are staged through LDS in depth chunks of
 // 16 frequency bins; inside a chunk lane l takes bins 8*(l/32) .. +8, read
 // as 16-byte vectors.  Tile index -> workgroup mapping keeps the channel
 // groups of one time tile on the same XCD so the panel tile is fetched once
@@ -52,18 +53,17 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wt = wave & 1, wc = wave >> 1;
   const int h = lane >> 5, c = lane & 31;
 
-  f32x16 acc[3][2][2];
+  // wave w multiplies time tile w (32 rows) by every live channel tile of
+  // the group, so all waves of a group do the same work
+  f32x16 acc[3][4][1];
 #pragma unroll
   for (int m = 0; m < 3; ++m)
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[m][i][j][e] = 0.f;
+      for (int e = 0; e < 16; ++e) acc[m][i][0][e] = 0.f;
 
   // global -> register staging: panel chunk 128 rows x 16 bins = 512 float4
   // (2 per thread); response chunk 3 x 128 x 16 = 1536 float4 (6 per thread)
@@ -103,10 +103,10 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
   GTOD_ST_D(0, rd0) GTOD_ST_D(1, rd1) GTOD_ST_B(0, rb0) GTOD_ST_B(1, rb1)   \
   GTOD_ST_B(2, rb2) GTOD_ST_B(3, rb3) GTOD_ST_B(4, rb4) GTOD_ST_B(5, rb5)
 
-  // channel tiles this wave owns that hold at least one real channel
-  bool live[2];
+  // channel tiles of the group that hold at least one real channel
+  bool live[4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) live[i] = (ch0 + wc * 64 + i * 32) < a.K;
+  for (int i = 0; i < 4; ++i) live[i] = (ch0 + i * 32) < a.K;
 
   {
     const int k0n = 0;
@@ -124,34 +124,30 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
     // two half-steps of 4 bins: lane takes bins 8*h + 4*hs + (0..3)
 #pragma unroll
     for (int hs = 0; hs < 2; ++hs) {
-      float4 dv[2];
+      const float4 dv = *reinterpret_cast<const float4*>(&sD[(wave * 32 + c) * LP + 8 * h + 4 * hs]);
+      float dsq[4];
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-        dv[j] = *reinterpret_cast<const float4*>(&sD[(wt * 64 + j * 32 + c) * LP + 8 * h + 4 * hs]);
+      for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = dv[s4] * dv[s4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
+      for (int i = 0; i < 4; ++i) {
         if (live[i]) {
           float4 bv[3];
 #pragma unroll
           for (int m = 0; m < 3; ++m)
             bv[m] = *reinterpret_cast<const float4*>(
-                &sB[(m * NT + wc * 64 + i * 32 + c) * LP + 8 * h + 4 * hs]);
+                &sB[(m * NT + i * 32 + c) * LP + 8 * h + 4 * hs]);
 #pragma unroll
           for (int s4 = 0; s4 < 4; ++s4) {
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-              const float d = dv[j][s4];
-              acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[0][s4], d, acc[0][i][j], 0, 0, 0);
-              acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[1][s4], d, acc[1][i][j], 0, 0, 0);
-              acc[2][i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[2][s4], d * d, acc[2][i][j], 0, 0, 0);
-            }
+            acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[0][s4], dv[s4], acc[0][i][0], 0, 0, 0);
+            acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[1][s4], dv[s4], acc[1][i][0], 0, 0, 0);
+            acc[2][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[2][s4], dsq[s4], acc[2][i][0], 0, 0, 0);
           }
         }
       }
     }
   }
 
-  contraction_epilogue(a, acc, smem, row0, ch0, wt, wc, live);
+  contraction_epilogue<4, 1>(a, acc, smem, row0 + wave * 32, ch0, live);
 }
 #undef GTOD_LD_D
 #undef GTOD_LD_B

@@ -11,14 +11,16 @@
 //   Z_k = (X_k + conj X_{M-k}) + i e^{2 pi i k/N} (X_k - conj X_{M-k}),
 // whose output z_m = x_{2m} + i x_{2m+1}.  The complex DFT uses the
 // four-step split M = M1 * M2 (M2 <= 4096), k = k1 + M1 k2, m = m1 M2 + m2:
-//   pass 1, per (series, k1): length-M2 DFT over k2 of Z (generated on the
-//     fly, so the stride costs nothing), times e^{2 pi i k1 m2 / M}, stored
-//     contiguous in m2;
+//   pass 1, per (series, column set closed under k -> M-k): the spectrum
+//     bins of those columns drawn once, Z built in place, length-M2 DFTs
+//     over k2 (the stride costs nothing as nothing is read), times
+//     e^{2 pi i k1 m2 / M}, stored contiguous in m2;
 //   pass 2, per (series, block of B2 consecutive m2): length-M1 DFTs over
 //     k1, read and written as runs of B2 consecutive m2.
 // With M1 = 1 pass 1 writes the output directly.  Each DFT runs in LDS as
-// radix-2 decimation in time on bit-reversed input, twiddles from a table
-// of e^{2 pi i m / L} evaluated with sincospi on exact arguments.
+// radix-2 decimation in frequency (pass 1, natural input) or in time (pass
+// 2, bit-reversed input), twiddles from a table of e^{2 pi i m / L}
+// evaluated with sincospi on exact arguments.
 #include <hip/hip_runtime.h>
 
 #include "gtod_internal.h"
@@ -69,19 +71,6 @@ __device__ void lds_dit(float2* buf, const float2* tw, int lg, int batch) {
   }
 }
 
-__device__ __forceinline__ float2 spectrum_bin(const PinkArgs& a, int64_t j,
-                                               int k, int p, float sc,
-                                               float alpha) {
-  if (j <= 0 || j >= a.M) return make_float2(0.f, 0.f);
-  const u32x4 o = philox10(u32x4{(uint32_t)j, (uint32_t)k, (uint32_t)p, 1u},
-                           a.key0, a.key1);
-  float zc, zs;
-  box_muller(o.x, o.y, &zc, &zs);
-  const float f = (float)j * (float)(a.fs / (double)a.N);
-  const float cj = sc * powf(f, -0.5f * alpha);
-  return make_float2(cj * zc, cj * zs);
-}
-
 __device__ __forceinline__ void store_out(const PinkArgs& a, int64_t series,
                                           int64_t m, float2 z) {
   const int64_t t = 2 * m;
@@ -96,41 +85,120 @@ __device__ __forceinline__ void store_out(const PinkArgs& a, int64_t series,
 
 }  // namespace
 
+// In-place inverse DFTs of `batch` contiguous transforms of length 2^lg,
+// natural-order input, bit-reversed output (decimation in frequency).
+__device__ void lds_dif(float2* buf, const float2* tw, int lg, int batch) {
+  const int L = 1 << lg;
+  const int half_total = (L >> 1) * batch;
+  for (int s = lg; s >= 1; --s) {
+    const int half = 1 << (s - 1);
+    const int tstride = L >> s;
+    for (int bf = threadIdx.x; bf < half_total; bf += blockDim.x) {
+      const int tr = bf / (L >> 1);
+      const int b = bf % (L >> 1);
+      const int pos = b % half;
+      const int i = tr * L + (b / half) * 2 * half + pos;
+      const int jx = i + half;
+      const float2 u = buf[i];
+      const float2 v = buf[jx];
+      buf[i] = make_float2(u.x + v.x, u.y + v.y);
+      buf[jx] = cmul(make_float2(u.x - v.x, u.y - v.y), tw[pos * tstride]);
+    }
+    __syncthreads();
+  }
+}
+
+// Pass 1 works on a set of columns closed under k -> M - k: column 0,
+// column M1/2, or the pair (k1, M1 - k1).  Each spectral bin X_j is drawn
+// once; every Z_k is built from X_k and X_{M-k} held in LDS, two at a time
+// (e^{2 pi i (M-k)/N} = -conj e^{2 pi i k/N}).
 __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
-  __shared__ float2 buf[kLdsC];
+  __shared__ float2 buf[2][kLdsC];
   __shared__ float2 tw[kLdsC / 2];
-  const int k1 = blockIdx.x;
+  const int grp = blockIdx.x;
   const int sl = blockIdx.y;
   const int64_t series = a.s0 + sl;
   const int p = (int)(series / a.K);
   const int k = (int)(series % a.K);
   const float sc = a.scale[k];
-  const float alpha = a.alpha[k];
-  const int M2 = a.M2;
+  const float halpha = -0.5f * a.alpha[k];
+  const float fstep = (float)(a.fs / (double)a.N);
+  const int M1 = a.M1, M2 = a.M2;
   const int lgN = a.lgM1 + a.lgM2 + 1;
+  // columns of this group: kind 0 = {0}, 1 = {M1/2}, 2 = {k1, M1 - k1}
+  int kind, col[2], ncol;
+  if (grp == 0) { kind = 0; col[0] = 0; ncol = 1; }
+  else if (grp == 1) { kind = 1; col[0] = M1 / 2; ncol = 1; }
+  else { kind = 2; col[0] = grp - 1; col[1] = M1 - (grp - 1); ncol = 2; }
+  col[1] = (ncol == 2) ? col[1] : col[0];
 
   for (int m = threadIdx.x; m < M2 / 2; m += blockDim.x) tw[m] = twiddle(m, a.lgM2);
-  for (int k2 = threadIdx.x; k2 < M2; k2 += blockDim.x) {
-    const int64_t kk = k1 + (int64_t)a.M1 * k2;
-    const float2 xa = spectrum_bin(a, kk, k, p, sc, alpha);
-    const float2 xb = spectrum_bin(a, a.M - kk, k, p, sc, alpha);
-    // E = X_k + conj(X_{M-k}), O = X_k - conj(X_{M-k})
-    const float2 ev = make_float2(xa.x + xb.x, xa.y - xb.y);
-    const float2 od = make_float2(xa.x - xb.x, xa.y + xb.y);
-    const float2 w = twiddle((uint32_t)kk, lgN);
-    const float2 wo = cmul(w, od);
-    buf[bitrev(k2, a.lgM2)] = make_float2(ev.x - wo.y, ev.y + wo.x);
+  // draw X for every bin of the group's columns (natural order)
+  for (int idx = threadIdx.x; idx < ncol * M2; idx += blockDim.x) {
+    const int c = idx / M2, k2 = idx % M2;
+    const int64_t j = col[c] + (int64_t)M1 * k2;
+    float2 x = make_float2(0.f, 0.f);
+    if (j > 0 && j < a.M) {
+      const u32x4 o = philox10(u32x4{(uint32_t)j, (uint32_t)k, (uint32_t)p, 1u},
+                               a.key0, a.key1);
+      float zc, zs;
+      box_muller(o.x, o.y, &zc, &zs);
+      const float cj = sc * exp2f(halpha * log2f((float)j * fstep));
+      x = make_float2(cj * zc, cj * zs);
+    }
+    buf[c][k2] = x;
   }
   __syncthreads();
-  lds_dit(buf, tw, a.lgM2, 1);
-  if (a.M1 == 1) {
-    for (int m2 = threadIdx.x; m2 < M2; m2 += blockDim.x) store_out(a, series, m2, buf[m2]);
-  } else {
-    float2* dst = a.scratch + ((int64_t)sl * a.M1 + k1) * M2;
-    const int lgM = a.lgM1 + a.lgM2;
-    for (int m2 = threadIdx.x; m2 < M2; m2 += blockDim.x) {
-      const uint32_t e = (uint32_t)(((uint64_t)k1 * m2) & ((1ull << lgM) - 1));
-      dst[m2] = cmul(buf[m2], twiddle(e, lgM));
+  // Z in place, one pair (k, M - k) per work item
+  const int U = kind == 0 ? M2 / 2 + 1 : (kind == 1 ? M2 / 2 : M2);
+  for (int u = threadIdx.x; u < U; u += blockDim.x) {
+    int ca, ra, cb, rb;   // (column slot, row) of k and of M - k
+    bool nyq = false;
+    if (kind == 0) {
+      ca = 0; ra = (u == M2 / 2 && M2 > 1) ? M2 / 2 : u;
+      if (u == 0 || M2 == 1) { nyq = true; cb = 0; rb = 0; }
+      else { cb = 0; rb = M2 - ra; }
+    } else if (kind == 1) {
+      ca = 0; ra = u; cb = 0; rb = M2 - 1 - u;
+    } else {
+      ca = 0; ra = u; cb = 1; rb = M2 - 1 - u;
+    }
+    const float2 xa = buf[ca][ra];
+    const float2 xb = nyq ? make_float2(0.f, 0.f) : buf[cb][rb];
+    const int64_t kk = col[ca] + (int64_t)M1 * ra;
+    const float2 w = twiddle((uint32_t)kk, lgN);
+    // Z_k = (X_k + conj X_{M-k}) + i w (X_k - conj X_{M-k})
+    const float2 ev = make_float2(xa.x + xb.x, xa.y - xb.y);
+    const float2 od = make_float2(xa.x - xb.x, xa.y + xb.y);
+    const float2 wo = cmul(w, od);
+    const float2 za = make_float2(ev.x - wo.y, ev.y + wo.x);
+    if (nyq || (ca == cb && ra == rb)) {
+      buf[ca][ra] = za;
+    } else {
+      // Z_{M-k} with twiddle -conj(w): E' = conj(E), O' = -conj(O)
+      const float2 wb = make_float2(-w.x, w.y);
+      const float2 evb = make_float2(ev.x, -ev.y);
+      const float2 odb = make_float2(-od.x, od.y);
+      const float2 wob = cmul(wb, odb);
+      buf[ca][ra] = za;
+      buf[cb][rb] = make_float2(evb.x - wob.y, evb.y + wob.x);
+    }
+  }
+  __syncthreads();
+  lds_dif(&buf[0][0], tw, a.lgM2, 1);
+  if (ncol == 2) lds_dif(&buf[1][0], tw, a.lgM2, 1);
+  const int lgM = a.lgM1 + a.lgM2;
+  for (int c = 0; c < ncol; ++c) {
+    const int k1 = col[c];
+    if (M1 == 1) {
+      for (int m2 = threadIdx.x; m2 < M2; m2 += blockDim.x)
+        store_out(a, series, m2, buf[c][bitrev(m2, a.lgM2)]);
+    } else {
+      float2* dst = a.scratch + ((int64_t)sl * M1 + k1) * M2;
+      for (int m2 = threadIdx.x; m2 < M2; m2 += blockDim.x) {
+        const uint32_t e = (uint32_t)(((uint64_t)k1 * m2) & ((1ull << lgM) - 1));
+        dst[m2] = cmul(buf[c][bitrev(m2, a.lgM2)], twiddle(e, lgM));
+      }
     }
   }
 }
@@ -158,7 +226,8 @@ __global__ __launch_bounds__(256) void k_pink_pass2(PinkArgs a) {
 }
 
 void launch_pink_pass1(const PinkArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_pink_pass1, dim3(a.M1, a.n_series), dim3(256), 0, s, a);
+  const int groups = a.M1 == 1 ? 1 : a.M1 / 2 + 1;
+  hipLaunchKernelGGL(k_pink_pass1, dim3(groups, a.n_series), dim3(256), 0, s, a);
 }
 
 void launch_pink_pass2(const PinkArgs& a, hipStream_t s) {
