@@ -11,8 +11,8 @@
 // (the lo x lo products and the low half of the small dP^2 term are below
 // the FP32 rounding of the result).  The deviations dP are a few percent
 // of P, so the 16-bit operands give about 1e-7 relative error on P_KID.
-// dP is split once, when a chunk is staged into LDS; the response halves
-// come pre-split from the spectral setup.
+// dP is split once per workgroup, when a chunk is staged into LDS; the
+// response halves come pre-split from the spectral setup.
 #include <hip/hip_runtime.h>
 
 #include "gtod_internal.h"
@@ -66,69 +66,72 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
 
   const int64_t Fp = a.Fp;
   const int64_t KF = (int64_t)a.Kp * Fp;
-  // panel chunk: 128 rows x 32 floats = 1024 float4, 4 per thread
+  // panel chunk: 128 rows x 32 floats = 1024 float4, 4 per thread;
   // response chunk: 5 x 128 x 32 bf16 = 2560 x 16 bytes, 10 per thread
-  float4 rd[4];
-  uint4 rb[10];
-  auto load_chunk = [&](int k0) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + q * 256;
-      const int row = idx >> 3, c4 = idx & 7;
-      rd[q] = *reinterpret_cast<const float4*>(a.panel + (row0 + row) * Fp + k0 + 4 * c4);
-    }
-#pragma unroll
-    for (int q = 0; q < 10; ++q) {
-      const int idx = tid + q * 256;
-      const int mm = idx >> 9, rem = idx & 511;
-      const int ch = rem >> 2, c8 = rem & 3;
-      const int gch = ch0 + ch;
-      // mm: 0 B0h, 1 B0l, 2 B1h, 3 B1l, 4 B2h
-      const uint16_t* base = (mm & 1) ? a.Bl : a.Bh;
-      const int m = mm >> 1;
-      if (gch < a.Kp)
-        rb[q] = *reinterpret_cast<const uint4*>(base + m * KF + (int64_t)gch * Fp + k0 + 8 * c8);
-      else
-        rb[q] = make_uint4(0u, 0u, 0u, 0u);
-    }
-  };
-  auto store_chunk = [&]() {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int idx = tid + q * 256;
-      const int row = idx >> 3, c4 = idx & 7;
-      const float x[4] = {rd[q].x, rd[q].y, rd[q].z, rd[q].w};
-      bf16x4 hi, lo, sq;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        hi[e] = (__bf16)x[e];
-        lo[e] = (__bf16)(x[e] - (float)hi[e]);
-        sq[e] = (__bf16)(x[e] * x[e]);
-      }
-      const int o = row * LPB + 4 * c4;
-      *reinterpret_cast<bf16x4*>(&sD[o]) = hi;
-      *reinterpret_cast<bf16x4*>(&sD[MT * LPB + o]) = lo;
-      *reinterpret_cast<bf16x4*>(&sD[2 * MT * LPB + o]) = sq;
-    }
-#pragma unroll
-    for (int q = 0; q < 10; ++q) {
-      const int idx = tid + q * 256;
-      const int mm = idx >> 9, rem = idx & 511;
-      const int ch = rem >> 2, c8 = rem & 3;
-      *reinterpret_cast<uint4*>(&sB[(mm * NT + ch) * LPB + 8 * c8]) = rb[q];
-    }
-  };
+  float4 rd0, rd1, rd2, rd3;
+  uint4 rb0, rb1, rb2, rb3, rb4, rb5, rb6, rb7, rb8, rb9;
+#define GTOD_LD_D(q, dst, k0n)                                               \
+  {                                                                          \
+    const int idx = tid + (q) * 256;                                         \
+    dst = *reinterpret_cast<const float4*>(                                  \
+        a.panel + (row0 + (idx >> 3)) * Fp + (k0n) + 4 * (idx & 7));         \
+  }
+#define GTOD_LD_B(q, dst, k0n)                                               \
+  {                                                                          \
+    const int idx = tid + (q) * 256;                                         \
+    const int mm = idx >> 9, rem = idx & 511;                                \
+    const int gch = ch0 + (rem >> 2);                                        \
+    /* mm: 0 B0h, 1 B0l, 2 B1h, 3 B1l, 4 B2h */                              \
+    const uint16_t* base = (mm & 1) ? a.Bl : a.Bh;                           \
+    dst = gch < a.Kp ? *reinterpret_cast<const uint4*>(                      \
+                           base + (mm >> 1) * KF + (int64_t)gch * Fp + (k0n) + 8 * (rem & 3)) \
+                     : make_uint4(0u, 0u, 0u, 0u);                           \
+  }
+// split dP into hi, lo and (dP^2) hi while staging it into LDS
+#define GTOD_ST_D(q, src)                                                    \
+  {                                                                          \
+    const int idx = tid + (q) * 256;                                         \
+    const float x_[4] = {src.x, src.y, src.z, src.w};                        \
+    bf16x4 hi_, lo_, sq_;                                                    \
+    _Pragma("unroll") for (int e = 0; e < 4; ++e) {                         \
+      hi_[e] = (__bf16)x_[e];                                                \
+      lo_[e] = (__bf16)(x_[e] - (float)hi_[e]);                              \
+      sq_[e] = (__bf16)(x_[e] * x_[e]);                                      \
+    }                                                                        \
+    const int o_ = (idx >> 3) * LPB + 4 * (idx & 7);                         \
+    *reinterpret_cast<bf16x4*>(&sD[o_]) = hi_;                               \
+    *reinterpret_cast<bf16x4*>(&sD[MT * LPB + o_]) = lo_;                    \
+    *reinterpret_cast<bf16x4*>(&sD[2 * MT * LPB + o_]) = sq_;                \
+  }
+#define GTOD_ST_B(q, src)                                                    \
+  {                                                                          \
+    const int idx = tid + (q) * 256;                                         \
+    const int mm = idx >> 9, rem = idx & 511;                                \
+    *reinterpret_cast<uint4*>(&sB[(mm * NT + (rem >> 2)) * LPB + 8 * (rem & 3)]) = src; \
+  }
+#define GTOD_LOAD_CHUNK(k0n)                                                 \
+  GTOD_LD_D(0, rd0, k0n) GTOD_LD_D(1, rd1, k0n) GTOD_LD_D(2, rd2, k0n)       \
+  GTOD_LD_D(3, rd3, k0n)                                                     \
+  GTOD_LD_B(0, rb0, k0n) GTOD_LD_B(1, rb1, k0n) GTOD_LD_B(2, rb2, k0n)       \
+  GTOD_LD_B(3, rb3, k0n) GTOD_LD_B(4, rb4, k0n) GTOD_LD_B(5, rb5, k0n)       \
+  GTOD_LD_B(6, rb6, k0n) GTOD_LD_B(7, rb7, k0n) GTOD_LD_B(8, rb8, k0n)       \
+  GTOD_LD_B(9, rb9, k0n)
+#define GTOD_STORE_CHUNK                                                     \
+  GTOD_ST_D(0, rd0) GTOD_ST_D(1, rd1) GTOD_ST_D(2, rd2) GTOD_ST_D(3, rd3)   \
+  GTOD_ST_B(0, rb0) GTOD_ST_B(1, rb1)                                       \
+  GTOD_ST_B(2, rb2) GTOD_ST_B(3, rb3) GTOD_ST_B(4, rb4) GTOD_ST_B(5, rb5)   \
+  GTOD_ST_B(6, rb6) GTOD_ST_B(7, rb7) GTOD_ST_B(8, rb8) GTOD_ST_B(9, rb9)
 
   bool live[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) live[i] = (ch0 + wc * 64 + i * 32) < a.K;
 
-  load_chunk(0);
+  GTOD_LOAD_CHUNK(0)
   for (int k0 = 0; k0 < a.Fp; k0 += KC) {
     __syncthreads();
-    store_chunk();
+    GTOD_STORE_CHUNK
     __syncthreads();
-    if (k0 + KC < a.Fp) load_chunk(k0 + KC);
+    if (k0 + KC < a.Fp) { GTOD_LOAD_CHUNK(k0 + KC) }
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
       const int col = 16 * s + 8 * h;
@@ -166,6 +169,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
 
   contraction_epilogue<2, 2>(a, acc, smem, row0 + wt * 64, ch0 + wc * 64, live);
 }
+#undef GTOD_LD_D
+#undef GTOD_LD_B
+#undef GTOD_ST_D
+#undef GTOD_ST_B
+#undef GTOD_LOAD_CHUNK
+#undef GTOD_STORE_CHUNK
 
 void launch_gemm_bf16(const GemmArgs& a, hipStream_t s) {
   const int64_t n_tt8 = round_up(a.n_tt, 8);

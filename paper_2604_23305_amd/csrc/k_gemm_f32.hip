@@ -69,20 +69,23 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
   // (2 per thread); response chunk 3 x 128 x 16 = 1536 float4 (6 per thread)
   const int64_t Fp = a.Fp;
   const int64_t KF = (int64_t)a.Kp * Fp;
-  float4 rd0, rd1, rb0, rb1, rb2, rb3, rb4, rb5;
-#define GTOD_LD_D(q, dst)                                                    \
+  // two staging register sets: chunk c lives in set (c & 1) from its load,
+  // issued two chunks ahead, until it is stored into LDS
+  float4 rdA0, rdA1, rbA0, rbA1, rbA2, rbA3, rbA4, rbA5;
+  float4 rdB0, rdB1, rbB0, rbB1, rbB2, rbB3, rbB4, rbB5;
+#define GTOD_LD_D(q, dst, k0n)                                               \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
     dst = *reinterpret_cast<const float4*>(a.panel + (row0 + (idx >> 2)) * Fp + \
-                                           k0n + 4 * (idx & 3));             \
+                                           (k0n) + 4 * (idx & 3));           \
   }
-#define GTOD_LD_B(q, dst)                                                    \
+#define GTOD_LD_B(q, dst, k0n)                                               \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
     const int m = idx >> 9, rem = idx & 511;                                 \
     const int gch = ch0 + (rem >> 2);                                        \
     dst = gch < a.Kp ? *reinterpret_cast<const float4*>(                     \
-                           a.B + m * KF + (int64_t)gch * Fp + k0n + 4 * (rem & 3)) \
+                           a.B + m * KF + (int64_t)gch * Fp + (k0n) + 4 * (rem & 3)) \
                      : make_float4(0.f, 0.f, 0.f, 0.f);                      \
   }
 #define GTOD_ST_D(q, src)                                                    \
@@ -96,54 +99,62 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
     const int m = idx >> 9, rem = idx & 511;                                 \
     *reinterpret_cast<float4*>(&sB[(m * NT + (rem >> 2)) * LP + 4 * (rem & 3)]) = src; \
   }
-#define GTOD_LOAD_CHUNK                                                      \
-  GTOD_LD_D(0, rd0) GTOD_LD_D(1, rd1) GTOD_LD_B(0, rb0) GTOD_LD_B(1, rb1)   \
-  GTOD_LD_B(2, rb2) GTOD_LD_B(3, rb3) GTOD_LD_B(4, rb4) GTOD_LD_B(5, rb5)
-#define GTOD_STORE_CHUNK                                                     \
-  GTOD_ST_D(0, rd0) GTOD_ST_D(1, rd1) GTOD_ST_B(0, rb0) GTOD_ST_B(1, rb1)   \
-  GTOD_ST_B(2, rb2) GTOD_ST_B(3, rb3) GTOD_ST_B(4, rb4) GTOD_ST_B(5, rb5)
+#define GTOD_LOAD_CHUNK(S, k0n)                                              \
+  GTOD_LD_D(0, rd##S##0, k0n) GTOD_LD_D(1, rd##S##1, k0n)                    \
+  GTOD_LD_B(0, rb##S##0, k0n) GTOD_LD_B(1, rb##S##1, k0n)                    \
+  GTOD_LD_B(2, rb##S##2, k0n) GTOD_LD_B(3, rb##S##3, k0n)                    \
+  GTOD_LD_B(4, rb##S##4, k0n) GTOD_LD_B(5, rb##S##5, k0n)
+#define GTOD_STORE_CHUNK(S)                                                  \
+  GTOD_ST_D(0, rd##S##0) GTOD_ST_D(1, rd##S##1) GTOD_ST_B(0, rb##S##0)       \
+  GTOD_ST_B(1, rb##S##1) GTOD_ST_B(2, rb##S##2) GTOD_ST_B(3, rb##S##3)       \
+  GTOD_ST_B(4, rb##S##4) GTOD_ST_B(5, rb##S##5)
 
   // channel tiles of the group that hold at least one real channel
   bool live[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) live[i] = (ch0 + i * 32) < a.K;
 
-  {
-    const int k0n = 0;
-    GTOD_LOAD_CHUNK
-  }
-  for (int k0 = 0; k0 < a.Fp; k0 += KC) {
-    __syncthreads();
-    GTOD_STORE_CHUNK
-    __syncthreads();
-    if (k0 + KC < a.Fp) {
-      const int k0n = k0 + KC;
-      GTOD_LOAD_CHUNK
+// one chunk: two half-steps of 4 bins; lane takes bins 8*h + 4*hs + (0..3)
+#define GTOD_COMPUTE_CHUNK \
+_Pragma("unroll") \
+    for (int hs = 0; hs < 2; ++hs) { \
+      const float4 dv = *reinterpret_cast<const float4*>(&sD[(wave * 32 + c) * LP + 8 * h + 4 * hs]); \
+      float dsq[4]; \
+_Pragma("unroll") \
+      for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = dv[s4] * dv[s4]; \
+_Pragma("unroll") \
+      for (int i = 0; i < 4; ++i) { \
+        if (live[i]) { \
+          float4 bv[3]; \
+_Pragma("unroll") \
+          for (int m = 0; m < 3; ++m) \
+            bv[m] = *reinterpret_cast<const float4*>( \
+                &sB[(m * NT + i * 32 + c) * LP + 8 * h + 4 * hs]); \
+_Pragma("unroll") \
+          for (int s4 = 0; s4 < 4; ++s4) { \
+            acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[0][s4], dv[s4], acc[0][i][0], 0, 0, 0); \
+            acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[1][s4], dv[s4], acc[1][i][0], 0, 0, 0); \
+            acc[2][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[2][s4], dsq[s4], acc[2][i][0], 0, 0, 0); \
+          } \
+        } \
+      } \
     }
 
-    // two half-steps of 4 bins: lane takes bins 8*h + 4*hs + (0..3)
-#pragma unroll
-    for (int hs = 0; hs < 2; ++hs) {
-      const float4 dv = *reinterpret_cast<const float4*>(&sD[(wave * 32 + c) * LP + 8 * h + 4 * hs]);
-      float dsq[4];
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = dv[s4] * dv[s4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        if (live[i]) {
-          float4 bv[3];
-#pragma unroll
-          for (int m = 0; m < 3; ++m)
-            bv[m] = *reinterpret_cast<const float4*>(
-                &sB[(m * NT + i * 32 + c) * LP + 8 * h + 4 * hs]);
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) {
-            acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[0][s4], dv[s4], acc[0][i][0], 0, 0, 0);
-            acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[1][s4], dv[s4], acc[1][i][0], 0, 0, 0);
-            acc[2][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[2][s4], dsq[s4], acc[2][i][0], 0, 0, 0);
-          }
-        }
-      }
+  const int n_chunks = a.Fp / KC;
+  GTOD_LOAD_CHUNK(A, 0)
+  if (n_chunks > 1) { GTOD_LOAD_CHUNK(B, KC) }
+  for (int kc = 0; kc < n_chunks; kc += 2) {
+    __syncthreads();
+    GTOD_STORE_CHUNK(A)
+    __syncthreads();
+    if (kc + 2 < n_chunks) { GTOD_LOAD_CHUNK(A, (kc + 2) * KC) }
+    GTOD_COMPUTE_CHUNK
+    if (kc + 1 < n_chunks) {
+      __syncthreads();
+      GTOD_STORE_CHUNK(B)
+      __syncthreads();
+      if (kc + 3 < n_chunks) { GTOD_LOAD_CHUNK(B, (kc + 3) * KC) }
+      GTOD_COMPUTE_CHUNK
     }
   }
 
@@ -153,8 +164,13 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
 #undef GTOD_LD_B
 #undef GTOD_ST_D
 #undef GTOD_ST_B
+#undef GTOD_LD_D
+#undef GTOD_LD_B
+#undef GTOD_ST_D
+#undef GTOD_ST_B
 #undef GTOD_LOAD_CHUNK
 #undef GTOD_STORE_CHUNK
+#undef GTOD_COMPUTE_CHUNK
 
 void launch_gemm_f32(const GemmArgs& a, hipStream_t s) {
   const int64_t n_tt8 = round_up(a.n_tt, 8);
