@@ -16,5 +16,6 @@ Modules
   tod      pointing, screen and source sampling, cascade, contraction,
            photon noise, TOD assembly
   pink     Timmer-Koenig 1/f series
+  skydip   brightness-temperature scale by a simulated skydip
 """
-from . import physics, filters, philox, tod, pink  # noqa: F401
+from . import physics, filters, philox, tod, pink, skydip  # noqa: F401

@@ -639,3 +639,80 @@ def test_source_sampled_at_full_pointing():
         g = ot.row_geometry(sc, p, np.array([0]))
         P = ot.source_power(s, g["az"], g["el"])
         np.testing.assert_allclose(P[0], s.cube[4, col], rtol=1e-9)
+
+
+# --------------------------------------------------------------------------
+# Kelvin output by skydip (section 2.7)
+# --------------------------------------------------------------------------
+def test_skydip_brightness_limits():
+    """A transparent sky has T_b = 0; an opaque one T_b = T_atm."""
+    from oracle import skydip as osd
+    sc = tiny_scenario(F=16, K=3)
+    sp = sc.spectral
+    sp.eta_z = np.vstack([np.ones(sc.F), np.full(sc.F, 1e-300)])
+    sp.pwv0_mm, sp.dpwv_mm = 0.0, 1.0
+    _, _, t_b = osd.sweep(sc, np.pi / 2, 0.0, 1.0, 2)
+    np.testing.assert_allclose(t_b[0], 0.0, atol=1e-12)
+    np.testing.assert_allclose(t_b[1], sp.t_atm_K, rtol=1e-12)
+
+
+def test_skydip_exact_for_single_bin_channels():
+    """Channels that see one frequency bin each make power exactly linear in
+    T_b: the fit reproduces every sweep point, with slope D_j / T_atm per
+    unit weight (D = power difference between opaque and clear sky)."""
+    from oracle import skydip as osd
+    F, K = 12, 4
+    sc = tiny_scenario(F=F, K=K, filt="matrix", stages=configs.cascade_c2())
+    m = np.zeros((F, K))
+    for k, j in enumerate((1, 4, 7, 10)):
+        m[j, k] = 0.3 + 0.1 * k
+    sc.spectral.filters.matrix = m
+    el = np.pi / 3
+    pwv, p_kid, t_b = osd.sweep(sc, el, 0.2, 2.5, 9)
+    a, b = osd.fit(p_kid, t_b)
+    np.testing.assert_allclose(a + b * t_b, p_kid, rtol=1e-12)
+    clear = ot.cascade(sc, np.ones((1, F)), None)[0]
+    opaque = ot.cascade(sc, np.zeros((1, F)), None)[0]
+    for k, j in enumerate((1, 4, 7, 10)):
+        wq = sc.spectral.w_hz[j] * m[j, k]
+        assert a[k] == pytest.approx(wq * clear[j], rel=1e-12)
+        assert b[k] == pytest.approx(wq * (opaque[j] - clear[j])
+                                     / sc.spectral.t_atm_K, rel=1e-12)
+
+
+def test_to_kelvin_inverts_the_line():
+    from oracle import skydip as osd
+    a = np.array([1.0, 2.0])
+    b = np.array([0.5, 4.0])
+    T = np.random.default_rng(0).uniform(0, 300, (3, 2, 7))
+    P = a[None, :, None] + b[None, :, None] * T
+    np.testing.assert_allclose(osd.to_kelvin(P, a, b), T, rtol=1e-14)
+
+
+def test_skydip_fit_matches_polyfit_and_flags_degenerate_channels():
+    """The closed-form fit agrees with numpy's least-squares polynomial fit;
+    a constant or undefined T_b column gives NaN."""
+    from oracle import skydip as osd
+    rng = np.random.default_rng(11)
+    t = rng.uniform(5, 60, (40, 4))
+    p = 3e-12 + 2e-14 * t + rng.normal(0, 1e-16, t.shape)
+    t[:, 2] = 7.0
+    t[:, 3] = np.nan
+    a, b = osd.fit(p, t)
+    for k in range(2):
+        bk, ak = np.polyfit(t[:, k], p[:, k], 1)
+        assert a[k] == pytest.approx(ak, rel=1e-10)
+        assert b[k] == pytest.approx(bk, rel=1e-10)
+    assert np.isnan(a[2:]).all() and np.isnan(b[2:]).all()
+
+
+def test_skydip_dead_channel_has_no_scale():
+    from oracle import skydip as osd
+    F, K = 12, 2
+    sc = tiny_scenario(F=F, K=K, filt="matrix")
+    m = np.zeros((F, K))
+    m[3, 0] = 0.5
+    sc.spectral.filters.matrix = m
+    a, b = osd.skydip(sc, np.pi / 3, 0.3, 2.0, 5)
+    assert np.isfinite(a[0]) and np.isfinite(b[0]) and b[0] > 0
+    assert np.isnan(a[1]) and np.isnan(b[1])
