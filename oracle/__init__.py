@@ -17,5 +17,6 @@ Modules
            photon noise, TOD assembly
   pink     Timmer-Koenig 1/f series
   skydip   brightness-temperature scale by a simulated skydip
+  reduce   common-mode atmosphere subtraction and inverse-variance gridding
 """
-from . import physics, filters, philox, tod, pink, skydip  # noqa: F401
+from . import physics, filters, philox, tod, pink, skydip, reduce  # noqa: F401

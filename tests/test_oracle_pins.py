@@ -716,3 +716,108 @@ def test_skydip_dead_channel_has_no_scale():
     a, b = osd.skydip(sc, np.pi / 3, 0.3, 2.0, 5)
     assert np.isfinite(a[0]) and np.isfinite(b[0]) and b[0] > 0
     assert np.isnan(a[1]) and np.isnan(b[1])
+
+
+# --------------------------------------------------------------------------
+# common-mode subtraction and gridding (section 4.3)
+# --------------------------------------------------------------------------
+def _reduce_scenario(T=400, P=7):
+    sc = tiny_scenario(F=30, K=4, P=P, T=T, filt="lorentz")
+    return sc
+
+
+def test_channel_transmission_single_bin_and_airmass():
+    """Single-bin channels see exactly that bin's table transmission; the
+    transmission at elevation 30 degrees is the zenith one squared, and at
+    the zenith it is the zenith one."""
+    from oracle import reduce as orr
+    F, K = 10, 3
+    sc = tiny_scenario(F=F, K=K, P=1, T=4, filt="matrix", scan="stare")
+    m = np.zeros((F, K))
+    bins = (2, 5, 8)
+    for k, j in enumerate(bins):
+        m[j, k] = 0.4
+    sc.spectral.filters.matrix = m
+    sp = sc.spectral
+    row = 37
+    pwv = sp.pwv0_mm + row * sp.dpwv_mm
+    ez = orr.channel_zenith_transmission(sc, pwv)
+    np.testing.assert_allclose(ez, sp.eta_z[row, list(bins)], rtol=1e-13)
+    sc.dtheta = np.zeros(1)
+    sc.scan.theta0 = np.pi / 2
+    np.testing.assert_allclose(orr.spaxel_transmission(sc, ez, np.arange(4))[0],
+                               np.repeat(ez[:, None], 4, axis=1), rtol=1e-14)
+    sc.scan.theta0 = np.pi / 6
+    np.testing.assert_allclose(orr.spaxel_transmission(sc, ez, np.arange(4))[0],
+                               np.repeat(ez[:, None] ** 2, 4, axis=1), rtol=1e-13)
+
+
+def test_common_mode_removes_a_common_atmosphere():
+    """T_b = T_sky(t, k) (1 - eta_i) + s_i with s = 0 off source gives
+    T* = s_i / eta_i on source and 0 off source, whatever T_sky is."""
+    from oracle import reduce as orr
+    sc = _reduce_scenario()
+    P, K, T = sc.n_pix, sc.K, sc.t_total
+    r_out = 10 * gen.ARCSEC            # hexagon: centre on, ring off
+    S = orr.off_source(sc, r_out)
+    assert S.sum() == P - 1 and not S[0]
+    pwv = 0.9
+    eta = orr.spaxel_transmission(sc, orr.channel_zenith_transmission(sc, pwv),
+                                  np.arange(T))
+    rng = np.random.default_rng(5)
+    t_sky = rng.uniform(250, 280, (K, T))
+    s = np.zeros((P, K, T))
+    s[0] = rng.normal(0, 1e-3, (K, T))
+    t_b = t_sky[None] * (1 - eta) + s
+    ts = orr.common_mode(sc, t_b, pwv, r_out)
+    np.testing.assert_allclose(ts[0], s[0] / eta[0], rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(ts[1:], 0.0, atol=1e-11)
+    with pytest.raises(ValueError):
+        orr.common_mode(sc, t_b, pwv, 1.0)
+
+
+def test_gridding_matches_brute_force_loops():
+    """Per-spaxel cell statistics against explicit per-sample loops."""
+    from oracle import reduce as orr
+    sc = _reduce_scenario(T=300, P=3)
+    rng = np.random.default_rng(9)
+    tod = rng.normal(1.0, 0.2, (3, sc.K, 300))
+    half, n = 50 * gen.ARCSEC, 5
+    count, mean, var = orr.spaxel_maps(sc, tod, half, n)
+    d = 2 * half / (n - 1)
+    for p in range(3):
+        acc = {}
+        for t in range(300):
+            phi = sc.scan.r_petal * np.cos(sc.scan.Omega * t / 160.0) * np.sin(sc.scan.omega * t / 160.0)
+            th = sc.scan.r_petal * np.sin(sc.scan.Omega * t / 160.0) * np.sin(sc.scan.omega * t / 160.0)
+            ix = int(np.floor((phi + sc.dphi[p] + half) / d + 0.5))
+            iy = int(np.floor((th + sc.dtheta[p] + half) / d + 0.5))
+            if 0 <= ix < n and 0 <= iy < n:
+                acc.setdefault(iy * n + ix, []).append(t)
+        for c in range(n * n):
+            ts = acc.get(c, [])
+            assert count[p, c] == len(ts)
+            for k in range(sc.K):
+                if len(ts) >= 2:
+                    v = tod[p, k, ts]
+                    assert mean[p, k, c] == pytest.approx(np.mean(v), rel=1e-12)
+                    assert var[p, k, c] == pytest.approx(np.var(v, ddof=1), rel=1e-10)
+                else:
+                    assert np.isnan(mean[p, k, c]) and np.isnan(var[p, k, c])
+    assert count.sum() > 0.8 * 3 * 300
+
+
+def test_inverse_variance_combination_closed_form():
+    """Two spaxels with identical cells: means m1, m2 with variances
+    s1^2 = 1, s2^2 = 4 over equal counts m combine to (4 m1 + m2) / 5 with
+    weight 5 m / 4; a cell only one spaxel reaches takes its mean."""
+    from oracle import reduce as orr
+    C = 3
+    count = np.array([[4.0, 4.0, 4.0], [4.0, 4.0, 1.0]])
+    mean = np.array([[[1.0, 2.0, 3.0]], [[3.0, -1.0, 9.0]]])
+    var = np.array([[[1.0, 1.0, 1.0]], [[4.0, 4.0, np.nan]]])
+    m, w = orr.combine(count, mean, var)
+    assert m.shape == (1, C)
+    np.testing.assert_allclose(m[0, :2], [(4 * 1 + 3) / 5, (4 * 2 - 1) / 5])
+    np.testing.assert_allclose(w[0, :2], [5.0, 5.0])
+    assert m[0, 2] == 3.0 and w[0, 2] == 4.0
