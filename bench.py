@@ -25,6 +25,10 @@ METRIC = ("detector-samples/s (t×pix×chan) at ≤1e-6 rel err vs "
           "FP64; p50/p99 request ms")
 PEAK = {"fp32": 157.3e12, "split": 2.5e15}   # dense MFMA FLOP/s (MI355X)
 HBM_PEAK = 8.0e12
+SKYDIP_PWV = (0.25, 2.75)
+ARCSEC = 3.141592653589793 / 180.0 / 3600.0
+REDUCE_R_OUT = 30 * ARCSEC       # outer ring of the 7x7 grid is off source
+REDUCE_MAP = (31, 150 * ARCSEC)  # nodes per axis, half extent
 
 WORKLOADS = {
     "c2": "single-pixel spectrometer: 1 px raster +-60\" at 0.5 deg/s, "
@@ -55,6 +59,14 @@ def parse():
     ap.add_argument("--workspace-gib", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--kelvin", type=int, default=0, metavar="N",
+                    help="output in kelvin: calibrate by an N-point skydip "
+                         "(PWV 0.25-2.75 mm at the scan elevation) before "
+                         "the timed steps")
+    ap.add_argument("--reduce", action="store_true",
+                    help="after the simulation steps, time gtod_reduce "
+                         "(common-mode subtraction + 31x31 inverse-variance "
+                         "maps) on the Kelvin TOD; needs --kelvin")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter "
                          "calibration for HBM byte counts)")
@@ -66,18 +78,23 @@ def scenario(name):
     return {"c2": configs.c2, "c3": configs.c3, "c4": configs.c4}[name]()
 
 
+def _cores():
+    """Threads the oracle's BLAS/FFT pools use."""
+    try:
+        import numpy  # noqa: F401  (loads the BLAS pool)
+        from threadpoolctl import threadpool_info
+        return int(max([i.get("num_threads", 1) for i in threadpool_info()]
+                       or [1]))
+    except Exception:  # pragma: no cover
+        return os.cpu_count() or 1
+
+
 def cpu_baseline(sc, target_s):
     """The FP64 oracle, as it is, on a bounded sample of the same workload:
     all pixels over a window of samples in the middle of the observation,
     plus two full 1/f series; scaled to detector-samples/s."""
-    import numpy as np
     import oracle
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([i.get("num_threads", 1) for i in threadpool_info()]
-                      or [1])
-    except Exception:  # pragma: no cover
-        threads = os.cpu_count() or 1
+    threads = _cores()
     mid = sc.t_total // 2
     # size the window from the marginal cost per sample (each call also
     # rebuilds the oracle's channel responses, a fixed cost)
@@ -111,10 +128,75 @@ def cpu_baseline(sc, target_s):
                        f"detector-sample")}
 
 
+def cpu_skydip(sc, n):
+    """Seconds the oracle takes for the same skydip calibration."""
+    from oracle import skydip as osd
+    t = time.perf_counter()
+    osd.skydip(sc, sc.scan.theta0, *SKYDIP_PWV, n)
+    return time.perf_counter() - t
+
+
+def run_reduce(args, g, torch, ctx, run, sc, out, stream, steps=3):
+    """Time gtod_reduce on the Kelvin TOD of the last simulation step."""
+    n, half = REDUCE_MAP
+    ts = torch.empty_like(out.tod)
+    mp = torch.zeros((sc.K, n, n), dtype=torch.float64, device="cuda")
+    wt = torch.zeros_like(mp)
+    d = run.reduce_desc(out.tod, REDUCE_R_OUT, t_star=ts, maps=(mp, wt),
+                        map_n=n, map_half_rad=half, pwv=out.pwv)
+    g.reduce(ctx, d, stream)
+    torch.cuda.synchronize()
+    g.profile_enable(ctx, True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record(stream)
+    for _ in range(steps):
+        g.reduce(ctx, d, stream)
+    ev[1].record(stream)
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / steps
+    prof = g.profile_read(ctx)
+    g.profile_enable(ctx, False)
+    kern = {k: v for k, v in kernel_table(prof).items()
+            if k in ("common", "grid")}
+    dom = max(kern, key=lambda k: kern[k]["total_ms"])
+    k = kern[dom]
+    det = sc.n_pix * sc.K * sc.t_total
+    finite = int(torch.isfinite(mp).sum().item())
+    del ts
+    return {"det_samples_per_s": det / (ms / 1e3), "ms_per_call": ms,
+            "calls": steps, "map_nodes": n,
+            "map_half_arcsec": half / ARCSEC,
+            "r_out_arcsec": REDUCE_R_OUT / ARCSEC,
+            "finite_map_cells": finite, "kernels": kern,
+            "roofline": {"kernel": dom, "bound": "hbm",
+                         "achieved": k["alg_gbs"], "peak": HBM_PEAK / 1e9,
+                         "unit": "GB/s", "frac": k["alg_gbs"] * 1e9 / HBM_PEAK,
+                         "traffic": None}}
+
+
+def cpu_reduce(sc, seconds_hint=None):
+    """The oracle's common-mode subtraction and gridding on one channel of
+    every spaxel over 120000 samples of a synthetic Kelvin TOD."""
+    import numpy as np
+    from oracle import reduce as orr
+    T = min(sc.t_total, 120000)
+    rng = np.random.default_rng(0)
+    tb = (20.0 + rng.normal(0, 0.01, (sc.n_pix, 1, T))).astype(np.float32)
+    n, half = REDUCE_MAP
+    t = time.perf_counter()
+    ts = orr.common_mode(sc, tb, 1.0, REDUCE_R_OUT, channels=[sc.K // 2])
+    orr.combine(*orr.spaxel_maps(sc, ts, half, n))
+    dt = time.perf_counter() - t
+    return {"value": sc.n_pix * T / dt, "unit": "detector-samples/s",
+            "kind": "oracle", "cores": _cores(),
+            "sample": f"1 channel x {sc.n_pix} spaxels x {T} samples"}
+
+
 def kernel_table(prof):
     """Per-kernel figures from the library's event timing, with the
     algorithmic work the library reports per kernel (FLOP for the
-    contractions, bytes for the panel, complex points for the 1/f passes:
+    contractions, bytes for the panel and the reduction kernels, complex
+    points for the 1/f passes:
     an 8-byte scratch write in pass 1; a scratch read plus the in-place add
     into the TOD, 16 bytes, in pass 2)."""
     kern = {}
@@ -125,7 +207,7 @@ def kernel_table(prof):
         sec = ms / 1e3
         if name.startswith("gemm"):
             d["alg_tflops"] = units / sec / 1e12
-        elif name == "panel":
+        elif name in ("panel", "common", "grid"):
             d["alg_gbs"] = units / sec / 1e9
         else:
             d["alg_gbs"] = (8.0 if name == "pink_pass1" else 16.0) * units / sec / 1e9
@@ -248,8 +330,24 @@ def main():
     ctx = g.sim_init(device=0, precision=prec,
                      workspace_bytes=int(args.workspace_gib * (1 << 30)))
     run = g.ScenarioRun(ctx, sc)
-    out = run.alloc()
-    jobs = [run.signal_job(out), run.pink_job(out.tod, accumulate=True)]
+    if args.reduce and not args.kelvin:
+        print("--reduce needs --kelvin N", file=sys.stderr)
+        sys.exit(2)
+    out = run.alloc(with_pwv=args.reduce)
+    kel = None
+    if args.kelvin:
+        times = []
+        for _ in range(3):
+            t = time.perf_counter()
+            g.skydip(ctx, run.spec_id, sc.K, sc.scan.theta0, *SKYDIP_PWV,
+                     args.kelvin)
+            times.append(time.perf_counter() - t)
+        kel = {"sweep_points": args.kelvin, "pwv_mm": list(SKYDIP_PWV),
+               "elevation_deg": float(np.degrees(sc.scan.theta0)),
+               "skydip_ms": min(times) * 1e3}
+    kflag = bool(args.kelvin)
+    jobs = [run.signal_job(out, kelvin=kflag),
+            run.pink_job(out.tod, accumulate=True, kelvin=kflag)]
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t_setup
@@ -281,6 +379,8 @@ def main():
 
     kern = kernel_table(prof)
     roof = roofline(kern, args.workload)
+    red = run_reduce(args, g, torch, ctx, run, sc, out, stream) \
+        if args.reduce else None
 
     res = {
         "metric": METRIC,
@@ -298,6 +398,7 @@ def main():
         "config": {"workload": f"{args.workload}: {WORKLOADS[args.workload]}",
                    "pixels": sc.n_pix, "channels": sc.K, "freq_bins": sc.F,
                    "samples": sc.t_total, "precision": prec_name,
+                   "tod_unit": "K" if kel else "W",
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
                        "p99": float(np.percentile(step_ms, 99))},
@@ -307,8 +408,16 @@ def main():
     g.free(ctx)
     del out
     torch.cuda.empty_cache()
+    if kel:
+        res["kelvin"] = kel
+    if red:
+        res["reduce"] = red
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+        if kel:
+            kel["skydip_oracle_ms"] = cpu_skydip(sc, args.kelvin) * 1e3
+        if red:
+            red["cpu_baseline"] = cpu_reduce(sc)
     print(json.dumps(res), flush=True)
 
 

@@ -44,6 +44,7 @@ typedef int32_t gtod_status;
                                    leaves the table (STRICT_RANGE only)   */
 #define GTOD_EDEVICE (-6)       /* HIP runtime error                      */
 #define GTOD_EUNSUPPORTED (-7)  /* device is not gfx950                   */
+#define GTOD_EIO (-8)           /* output file could not be written        */
 
 typedef struct gtod_ctx gtod_ctx;
 
@@ -205,12 +206,17 @@ gtod_status gtod_load_filters(gtod_ctx* ctx, const gtod_spectral_desc* desc,
 /* job flags */
 #define GTOD_JOB_PHOTON_NOISE 1u  /* add sigma*z (SIGNAL)                 */
 #define GTOD_JOB_ACCUMULATE 2u    /* add into tod instead of overwriting  */
+#define GTOD_JOB_KELVIN 4u        /* tod in K on the skydip scale (SIGNAL:
+                                     (P - a_k) / b_k plus noise / b_k;
+                                     PINK: noise / b_k); needs gtod_skydip */
 
 /*
  * One unit of work for gtod_simulate_tod.
  *
  * Pixels: n_pix spaxels with pointing offsets dphi_rad/dtheta_rad (host
- *   [n_pix]).  Pixel p of the job keys the noise counters.
+ *   [n_pix]).  Pixel p of the job keys the noise counters as pixel
+ *   pix0 + p, so that a job covering spaxels [pix0, pix0 + n_pix) of a
+ *   larger array draws the same noise as one job over the whole array.
  * Scan: (phi(t), theta(t)) around the scan offset (phi0, theta0), t =
  *   n / f_sample for absolute sample n.  Screen coordinates use
  *   phi(t)+dphi, theta(t)+dtheta (Eq. xy_atm); the airmass and the source
@@ -229,8 +235,9 @@ gtod_status gtod_load_filters(gtod_ctx* ctx, const gtod_spectral_desc* desc,
  * Outputs (device, caller-owned; layout [n_pix][K][out_ld], time fastest,
  *   holding samples [out_t0, out_t0 + out_ld); out_ld = 0 means out_t0 = 0
  *   and out_ld = t_total):
- *   tod (required): power (+ noise) in W.  p_kid, sigma (optional, SIGNAL):
- *   noise-free power and photon-noise sigma.  pwv (optional, SIGNAL):
+ *   tod (required): power (+ noise) in W, or brightness temperature in K
+ *   with GTOD_JOB_KELVIN.  p_kid, sigma (optional, SIGNAL): noise-free
+ *   power and photon-noise sigma, always in W.  pwv (optional, SIGNAL):
  *   [n_pix][out_ld] zenith PWV sampled at each row.
  *   SIGNAL needs out_t0 <= t_begin and t_end <= out_t0 + out_ld; PINK
  *   needs out_t0 = 0 and out_ld >= t_total.
@@ -254,7 +261,7 @@ typedef struct gtod_job {
   int64_t t_begin, t_end, t_total;
   uint64_t seed;
   uint32_t flags;
-  int32_t reserved0;
+  int32_t pix0;               /* noise-key index of pixel 0 (default 0)   */
   const double* pink_alpha;
   double pink_knee_hz;
   int64_t out_t0, out_ld;
@@ -275,6 +282,137 @@ typedef struct gtod_job {
  */
 gtod_status gtod_simulate_tod(gtod_ctx* ctx, const gtod_job* jobs,
                               int32_t n_jobs, void* hip_stream);
+
+/*
+ * gtod_skydip -- brightness-temperature scale of a spectral setup by a
+ * simulated skydip (section 2.7): the sky brightness is varied through the
+ * zenith PWV while the detected power is recorded, and a linear map between
+ * power and line-of-sight brightness temperature is fitted per channel.
+ *
+ * Sweep: n zenith PWV values evenly spaced over [pwv_lo_mm, pwv_hi_mm]
+ *   (both ends included) at elevation el_rad (airmass 1/sin el), no
+ *   source, no noise; PWV outside the table axis is clamped to it (ERANGE
+ *   instead under GTOD_INIT_STRICT_RANGE).
+ * Row i, channel k (all FP64):
+ *   p_kid[i][k] = sum_j w_j eta_jk P_j,   P = cascade output (Eq. radtrans)
+ *   t_b[i][k]   = T_atm sum_j w_j eta_jk (1 - eta_atm,j) / sum_j w_j eta_jk
+ * Fit: least-squares line p_kid = a_k + b_k t_b over the n rows.  A channel
+ *   with no response, or whose t_b does not vary, gets a_k = b_k = NaN.
+ * The scale is kept with the spectral setup (replacing an earlier one) and
+ *   used by jobs with GTOD_JOB_KELVIN.
+ * Outputs (host, caller-owned, each may be NULL): a_out, b_out [K] in W and
+ *   W/K; p_kid_out, t_b_out [n][K] in W and K.
+ * Synchronous: waits for all work on the device first, allocates
+ *   2 n F + 2 n K doubles of temporaries for the call.  A call that runs
+ *   while another host thread enqueues KELVIN jobs of the same setup races.
+ * Errors: ENOTFOUND, EINVAL (el_rad outside (0, pi), pwv_lo_mm >= pwv_hi_mm,
+ *   n outside [2, GTOD_SKYDIP_MAX_N]), ERANGE, EBUDGET, ENOMEM, EDEVICE.
+ */
+#define GTOD_SKYDIP_MAX_N 16384
+gtod_status gtod_skydip(gtod_ctx* ctx, int32_t spec_id, double el_rad,
+                        double pwv_lo_mm, double pwv_hi_mm, int32_t n,
+                        double* a_out, double* b_out, double* p_kid_out,
+                        double* t_b_out);
+
+/*
+ * gtod_reduce -- common-mode atmosphere subtraction and inverse-variance
+ * gridding of a brightness-temperature TOD (section 4.3, Eqs. common_mode
+ * and Sj), enqueued on hip_stream.
+ *
+ * Input: tod [n_pix][K][ld] in K (a GTOD_JOB_KELVIN output of the same
+ *   spectral setup and scan) holding samples [t0, t0 + T) of the
+ *   observation.  The scan (scan_kind, scan_params, theta0_rad, traj with
+ *   t_total rows) and the spaxel offsets (host [n_pix]) are those of the
+ *   simulation.
+ * Atmosphere: the mean zenith PWV is the mean of pwv (device [n_pix]
+ *   [pwv_ld], its first pwv_len columns: the SIGNAL job's PWV output), or
+ *   pwv_mean_mm when pwv is NULL.  Channel k's zenith transmission is the
+ *   response-weighted mean of the table's transmission at that PWV, and
+ *   spaxel i sees eta_i = eta_z,k ^ (1 / sin(theta(t) + theta0 + dtheta_i)).
+ * Common mode: S_j = 1 for the spaxels with sqrt(dphi^2 + dtheta^2) >
+ *   r_out_rad (at least one is required), and
+ *     T*_i = T_b,i / eta_i - (1 - eta_i) / (eta_i N_out)
+ *            sum_j S_j T_b,j / (1 - eta_j).
+ *   t_star (device [n_pix][K][ld], optional) receives T* in K.
+ * Maps (optional; map and weight both NULL or both set, device
+ *   [K][map_n][map_n], FP64): sample t of spaxel i falls in the nearest
+ *   node of the map_n x map_n grid spanning +-map_half_rad around the
+ *   pointing centre, at (phi(t) + dphi_i, theta(t) + dtheta_i); samples
+ *   more than half a node spacing outside the grid are dropped.  Per
+ *   spaxel, channel and cell the samples' mean and unbiased variance s^2
+ *   (m >= 2 samples, s^2 > 0) give weight m / s^2; map = sum w mean /
+ *   sum w over the spaxels, weight = sum w (NaN and 0 for no contribution).
+ *   Cell sums use LDS atomics, so maps can differ between runs in the last
+ *   bits.
+ * Uses the stream's workspace (channels are processed in groups that fit).
+ * Errors: EINVAL (shapes, no output requested, map_n outside
+ *   [2, GTOD_MAP_MAX_N], no off-source spaxel, workspace too small for one
+ *   channel), ENOTFOUND, EBUDGET, EDEVICE.
+ */
+#define GTOD_MAP_MAX_N 48
+typedef struct gtod_reduce_desc {
+  int32_t spec_id;
+  int32_t n_pix;
+  const double* dphi_rad;      /* host [n_pix] */
+  const double* dtheta_rad;    /* host [n_pix] */
+  int32_t scan_kind;
+  int32_t map_n;
+  double theta0_rad;
+  double scan_params[8];
+  const double* traj;          /* device [t_total][2] for GTOD_SCAN_TRAJ */
+  int64_t t_total;
+  int64_t t0, T, ld;
+  const float* tod;            /* device [n_pix][K][ld], K */
+  const float* pwv;            /* device [n_pix][pwv_ld] or NULL */
+  int64_t pwv_ld, pwv_len;
+  double pwv_mean_mm;
+  double r_out_rad;
+  double map_half_rad;
+  float* t_star;               /* device [n_pix][K][ld] or NULL */
+  double* map;                 /* device [K][map_n][map_n] or NULL */
+  double* weight;              /* device [K][map_n][map_n] or NULL */
+} gtod_reduce_desc;
+gtod_status gtod_reduce(gtod_ctx* ctx, const gtod_reduce_desc* desc,
+                        void* hip_stream);
+
+/*
+ * gtod_simulate_to_disk -- out-of-core run: simulate a whole observation
+ * in pixel groups and stream each group's TOD device -> pinned host ->
+ * disk, for outputs larger than the HBM one wants to give them (the
+ * paper's RAM manager, section 1, and its output files, section 2.7).
+ *
+ * signal: a SIGNAL job over the whole observation (t_begin = 0, t_end =
+ *   t_total; its output pointers and pix0 are ignored).  pink: NULL, or a
+ *   PINK job of the same spec_id, n_pix, t_total and seed.  KELVIN and
+ *   PHOTON_NOISE flags apply as in gtod_simulate_tod.
+ * Groups: pixels [g G, g G + G) with G = pix_per_group, or as many as
+ *   device_bytes allows for two slabs (n_pix_group x K x t_total floats,
+ *   plus n_pix_group x t_total for the PWV); each group runs as one
+ *   gtod_simulate_tod call with pix0 = g G, so the file holds exactly what
+ *   one in-memory run over all pixels would give.  While group g + 1 is
+ *   computed, group g is copied to host through host_bytes of pinned
+ *   staging (two halves) and written by a writer thread.
+ * Files in dir (created or overwritten, NumPy .npy format version 1.0):
+ *   tod.npy  float32 [n_pix][K][t_total] (W, or K with GTOD_JOB_KELVIN)
+ *   pwv.npy  float32 [n_pix][t_total] zenith PWV (GTOD_SINK_PWV)
+ *   time.npy float64 [t_total] seconds from the start (n / f_sample)
+ * Synchronous: returns when every file is complete.  stats (host [4], may
+ *   be NULL): wall seconds, bytes written, groups, pixels per group.
+ * Errors: EINVAL (jobs, a group of one pixel does not fit device_bytes,
+ *   host_bytes < 2 MiB), EBUDGET, ENOMEM, EIO (files), EDEVICE, and the
+ *   errors of gtod_simulate_tod.
+ */
+#define GTOD_SINK_PWV 1u
+typedef struct gtod_sink_desc {
+  const char* dir;
+  uint64_t device_bytes;
+  uint64_t host_bytes;
+  uint32_t flags;
+  int32_t pix_per_group;      /* 0: as many as device_bytes allows        */
+} gtod_sink_desc;
+gtod_status gtod_simulate_to_disk(gtod_ctx* ctx, const gtod_job* signal,
+                                  const gtod_job* pink,
+                                  const gtod_sink_desc* sink, double* stats);
 
 /* object kinds for gtod_free */
 #define GTOD_OBJ_SCREEN 0
@@ -318,19 +456,23 @@ gtod_status gtod_philox(gtod_ctx* ctx, const uint32_t* ctr, uint32_t* out,
  * algorithmic work: for the panel, bytes (20F + 32 per row: four source
  * spectra, the deviation row, four screen values); for the contractions,
  * FLOP (6 K F per row: three products); for the 1/f passes, complex
- * points. */
+ * points; for the common-mode and gridding kernels of gtod_reduce, bytes
+ * (4 per TOD sample read, 4 per T* sample written, 8 per channel and sample
+ * of the common-mode term, 16 per spaxel, channel and cell of statistics). */
 #define GTOD_KERNEL_PANEL 0
 #define GTOD_KERNEL_GEMM_F32 1
 #define GTOD_KERNEL_GEMM_BF16 2
 #define GTOD_KERNEL_PINK1 3
 #define GTOD_KERNEL_PINK2 4
-#define GTOD_N_KERNELS 5
+#define GTOD_KERNEL_COMMON 5
+#define GTOD_KERNEL_GRID 6
+#define GTOD_N_KERNELS 7
 gtod_status gtod_profile_enable(gtod_ctx* ctx, int32_t enable);
 gtod_status gtod_profile_read(gtod_ctx* ctx, double* out, int32_t n_kernels);
 
 /* sizeof of the descriptor structs, for binding checks (no device use):
- * out[0..4] = init, screen, stage, spectral, job. */
-void gtod_abi_sizes(int64_t out[5]);
+ * out[0..5] = init, screen, stage, spectral, job, reduce. */
+void gtod_abi_sizes(int64_t out[6]);
 
 #ifdef __cplusplus
 }

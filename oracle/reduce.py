@@ -58,13 +58,15 @@ def off_source(sc, r_out):
     return np.hypot(np.asarray(sc.dphi), np.asarray(sc.dtheta)) > r_out
 
 
-def common_mode(sc, t_b, pwv_mm, r_out, t0=0):
+def common_mode(sc, t_b, pwv_mm, r_out, t0=0, channels=None):
     """T*_a,i(t, k) of Eq. common_mode for a [P][K][T] Kelvin TOD holding
-    samples t0 .. t0 + T - 1."""
+    samples t0 .. t0 + T - 1 (or only the listed channels)."""
     t_b = np.asarray(t_b, dtype=np.float64)
     T = t_b.shape[2]
-    eta = spaxel_transmission(sc, channel_zenith_transmission(sc, pwv_mm),
-                              t0 + np.arange(T))
+    eta_zk = channel_zenith_transmission(sc, pwv_mm)
+    if channels is not None:
+        eta_zk = eta_zk[list(channels)]
+    eta = spaxel_transmission(sc, eta_zk, t0 + np.arange(T))
     S = off_source(sc, r_out)
     n_out = int(S.sum())
     if n_out == 0:

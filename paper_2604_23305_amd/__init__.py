@@ -4,6 +4,7 @@ C-ABI (include/gtod.h), with a thin ctypes binding."""
 from .binding import (GtodError, Outputs, ScenarioRun, abi_sizes,  # noqa
                       counters, free, load_filters, load_screen, memory,
                       philox, profile_enable, profile_read, sim_init,
-                      simulate_tod, spec_nep2_ref)
+                      reduce, simulate_to_disk, simulate_tod, skydip,
+                      spec_nep2_ref)
 from ._abi import (PREC_FP32, PREC_SPLIT_BF16, OBJ_CTX, OBJ_SCREEN,  # noqa
                    OBJ_SPEC, LIB_PATH)

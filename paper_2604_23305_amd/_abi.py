@@ -10,18 +10,20 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgtod.so")
 
-OK, EINVAL, ENOMEM, EBUDGET, ENOTFOUND, ERANGE, EDEVICE, EUNSUPPORTED = \
-    0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOMEM, EBUDGET, ENOTFOUND, ERANGE, EDEVICE, EUNSUPPORTED, EIO = \
+    0, -1, -2, -3, -4, -5, -6, -7, -8
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EBUDGET",
                 -4: "ENOTFOUND", -5: "ERANGE", -6: "EDEVICE",
-                -7: "EUNSUPPORTED"}
+                -7: "EUNSUPPORTED", -8: "EIO"}
+SINK_PWV = 1
 PREC_FP32, PREC_SPLIT_BF16 = 0, 1
 INIT_STRICT_RANGE = 1
 STAGE_REFLECT, STAGE_ATM_COUPLED, STAGE_OHMIC, STAGE_REFRACTIVE = 0, 1, 2, 3
 FILT_LORENTZ, FILT_FILTERBANK, FILT_MATRIX = 0, 1, 2
 JOB_SIGNAL, JOB_PINK = 0, 1
 SCAN_STARE, SCAN_DAISY, SCAN_TRAJ = 0, 1, 2
-JOB_PHOTON_NOISE, JOB_ACCUMULATE = 1, 2
+JOB_PHOTON_NOISE, JOB_ACCUMULATE, JOB_KELVIN = 1, 2, 4
+SKYDIP_MAX_N = 16384
 OBJ_SCREEN, OBJ_SPEC, OBJ_CTX = 0, 1, 2
 
 _dp = C.POINTER(C.c_double)
@@ -83,19 +85,44 @@ class Job(C.Structure):
                 ("el0_rad", C.c_double), ("del_rad", C.c_double),
                 ("t_begin", C.c_int64), ("t_end", C.c_int64),
                 ("t_total", C.c_int64), ("seed", C.c_uint64),
-                ("flags", C.c_uint32), ("reserved0", C.c_int32),
+                ("flags", C.c_uint32), ("pix0", C.c_int32),
                 ("pink_alpha", C.c_void_p), ("pink_knee_hz", C.c_double),
                 ("out_t0", C.c_int64), ("out_ld", C.c_int64),
                 ("tod", C.c_void_p), ("p_kid", C.c_void_p),
                 ("sigma", C.c_void_p), ("pwv", C.c_void_p)]
 
 
+class ReduceDesc(C.Structure):
+    _fields_ = [("spec_id", C.c_int32), ("n_pix", C.c_int32),
+                ("dphi_rad", C.c_void_p), ("dtheta_rad", C.c_void_p),
+                ("scan_kind", C.c_int32), ("map_n", C.c_int32),
+                ("theta0_rad", C.c_double),
+                ("scan_params", C.c_double * 8),
+                ("traj", C.c_void_p), ("t_total", C.c_int64),
+                ("t0", C.c_int64), ("T", C.c_int64), ("ld", C.c_int64),
+                ("tod", C.c_void_p), ("pwv", C.c_void_p),
+                ("pwv_ld", C.c_int64), ("pwv_len", C.c_int64),
+                ("pwv_mean_mm", C.c_double), ("r_out_rad", C.c_double),
+                ("map_half_rad", C.c_double),
+                ("t_star", C.c_void_p), ("map", C.c_void_p),
+                ("weight", C.c_void_p)]
+
+
+class SinkDesc(C.Structure):
+    _fields_ = [("dir", C.c_char_p), ("device_bytes", C.c_uint64),
+                ("host_bytes", C.c_uint64), ("flags", C.c_uint32),
+                ("pix_per_group", C.c_int32)]
+
+
 SYMBOLS = ["gtod_sim_init", "gtod_load_screen", "gtod_load_filters",
            "gtod_simulate_tod", "gtod_free", "gtod_last_error",
            "gtod_memory", "gtod_get_counters", "gtod_spec_nep2_ref",
            "gtod_philox", "gtod_abi_sizes", "gtod_profile_enable",
-           "gtod_profile_read"]
-KERNEL_NAMES = ["panel", "gemm_f32", "gemm_bf16", "pink_pass1", "pink_pass2"]
+           "gtod_profile_read", "gtod_skydip", "gtod_reduce",
+           "gtod_simulate_to_disk"]
+KERNEL_NAMES = ["panel", "gemm_f32", "gemm_bf16", "pink_pass1", "pink_pass2",
+                "common", "grid"]
+MAP_MAX_N = 48
 
 _lib = None
 
@@ -129,6 +156,12 @@ def load():
     lib.gtod_abi_sizes.restype = None
     lib.gtod_profile_enable.argtypes = [vp, C.c_int32]
     lib.gtod_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.c_int32]
+    lib.gtod_skydip.argtypes = [vp, C.c_int32, C.c_double, C.c_double,
+                                C.c_double, C.c_int32, vp, vp, vp, vp]
+    lib.gtod_reduce.argtypes = [vp, C.POINTER(ReduceDesc), vp]
+    lib.gtod_simulate_to_disk.argtypes = [vp, C.POINTER(Job), C.POINTER(Job),
+                                          C.POINTER(SinkDesc),
+                                          C.POINTER(C.c_double)]
     for name in SYMBOLS:
         if name not in ("gtod_last_error", "gtod_abi_sizes"):
             getattr(lib, name).restype = C.c_int32
@@ -138,4 +171,4 @@ def load():
 
 def struct_sizes():
     return [C.sizeof(InitDesc), C.sizeof(ScreenDesc), C.sizeof(Stage),
-            C.sizeof(SpectralDesc), C.sizeof(Job)]
+            C.sizeof(SpectralDesc), C.sizeof(Job), C.sizeof(ReduceDesc)]

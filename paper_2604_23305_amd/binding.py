@@ -16,7 +16,8 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 from . import _abi
-from ._abi import (JOB_ACCUMULATE, JOB_PHOTON_NOISE, JOB_PINK, JOB_SIGNAL,
+from ._abi import (JOB_ACCUMULATE, JOB_KELVIN, JOB_PHOTON_NOISE, JOB_PINK,
+                   JOB_SIGNAL,
                    OBJ_CTX, OBJ_SCREEN, OBJ_SPEC, PREC_FP32, PREC_SPLIT_BF16,
                    SCAN_DAISY, SCAN_STARE, SCAN_TRAJ)
 
@@ -175,6 +176,50 @@ def spec_nep2_ref(ctx, spec_id, K):
     return out
 
 
+def skydip(ctx, spec_id, K, el_rad, pwv_lo_mm, pwv_hi_mm, n,
+           return_sweep=False):
+    """Brightness-temperature scale of a spectral setup by a simulated
+    skydip; returns (a, b) per channel (P = a + b T_b), plus the sweep's
+    (p_kid, t_b) [n][K] with return_sweep.  Later KELVIN jobs of the setup
+    use this scale."""
+    lib = _abi.load()
+    a = np.zeros(K)
+    b = np.zeros(K)
+    pk = np.zeros((n, K)) if return_sweep else None
+    tb = np.zeros((n, K)) if return_sweep else None
+    _check(ctx, lib.gtod_skydip(ctx, spec_id, el_rad, pwv_lo_mm, pwv_hi_mm,
+                                n, _ptr(a), _ptr(b), _ptr(pk), _ptr(tb)))
+    return (a, b, pk, tb) if return_sweep else (a, b)
+
+
+def reduce(ctx, desc: _abi.ReduceDesc, stream=None):
+    """Enqueue gtod_reduce (common-mode subtraction and gridding)."""
+    lib = _abi.load()
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    _check(ctx, lib.gtod_reduce(ctx, C.byref(desc),
+                                C.c_void_p(stream.cuda_stream)))
+
+
+def simulate_to_disk(ctx, signal: _abi.Job, pink: Optional[_abi.Job], out_dir,
+                     device_bytes, host_bytes=256 << 20, pwv=True,
+                     pix_per_group=0):
+    """Out-of-core run: the whole observation in pixel groups, streamed to
+    out_dir/{tod,pwv,time}.npy.  Returns (wall s, bytes, groups, pixels
+    per group)."""
+    lib = _abi.load()
+    d = _abi.SinkDesc(dir=str(out_dir).encode(), device_bytes=device_bytes,
+                      host_bytes=host_bytes,
+                      flags=_abi.SINK_PWV if pwv else 0,
+                      pix_per_group=pix_per_group)
+    st = (C.c_double * 4)()
+    _check(ctx, lib.gtod_simulate_to_disk(
+        ctx, C.byref(signal), C.byref(pink) if pink is not None else None,
+        C.byref(d), st))
+    return st[0], int(st[1]), int(st[2]), int(st[3])
+
+
 def philox(ctx, ctr_dev, out_dev, n, seed, stream=None):
     lib = _abi.load()
     if stream is None:
@@ -201,7 +246,7 @@ def profile_read(ctx):
 
 def abi_sizes():
     lib = _abi.load()
-    out = (C.c_int64 * 5)()
+    out = (C.c_int64 * 6)()
     lib.gtod_abi_sizes(out)
     return list(out)
 
@@ -263,7 +308,8 @@ class ScenarioRun:
                        t0=t0, length=length)
 
     def signal_job(self, out: Outputs, t_begin=0, t_end=None, precision=-1,
-                   photon_noise=None, accumulate=False) -> _abi.Job:
+                   photon_noise=None, accumulate=False,
+                   kelvin=False) -> _abi.Job:
         sc = self.sc
         t_end = sc.t_total if t_end is None else t_end
         noise = sc.photon_noise if photon_noise is None else photon_noise
@@ -278,7 +324,8 @@ class ScenarioRun:
                      t_begin=t_begin, t_end=t_end, t_total=sc.t_total,
                      seed=sc.seed,
                      flags=(JOB_PHOTON_NOISE if noise else 0)
-                     | (JOB_ACCUMULATE if accumulate else 0),
+                     | (JOB_ACCUMULATE if accumulate else 0)
+                     | (JOB_KELVIN if kelvin else 0),
                      out_t0=out.t0, out_ld=out.length,
                      tod=out.tod.data_ptr(),
                      p_kid=out.p_kid.data_ptr() if out.p_kid is not None else None,
@@ -296,10 +343,48 @@ class ScenarioRun:
             j.az0_rad, j.daz_rad, j.el0_rad, j.del_rad = s.az0, s.daz, s.el0, s.del_
         return j
 
-    def pink_job(self, tod, accumulate=True) -> _abi.Job:
+    def reduce_desc(self, tod, r_out_rad, t_star=None, maps=None,
+                    map_n=31, map_half_rad=0.0, pwv=None, pwv_mean_mm=None,
+                    t0=0, T=None) -> _abi.ReduceDesc:
+        """Descriptor for gtod_reduce over this run's Kelvin TOD [P][K][ld]
+        holding samples [t0, t0 + T); maps = (map, weight) device float64
+        tensors [K][map_n][map_n]; the mean PWV comes from the pwv output
+        tensor [P][len] or from pwv_mean_mm."""
+        sc = self.sc
+        T = tod.shape[2] if T is None else T
+        kind = {"stare": SCAN_STARE, "daisy": SCAN_DAISY,
+                "traj": SCAN_TRAJ}[sc.scan.kind]
+        d = _abi.ReduceDesc(spec_id=self.spec_id, n_pix=sc.n_pix,
+                            dphi_rad=self.dphi.ctypes.data,
+                            dtheta_rad=self.dtheta.ctypes.data,
+                            scan_kind=kind, theta0_rad=sc.scan.theta0,
+                            t_total=sc.t_total, t0=t0, T=T,
+                            ld=tod.shape[2], tod=tod.data_ptr(),
+                            r_out_rad=r_out_rad,
+                            pwv_mean_mm=(float("nan") if pwv_mean_mm is None
+                                         else pwv_mean_mm))
+        d.scan_params[0] = sc.scan.r_petal
+        d.scan_params[1] = sc.scan.omega
+        d.scan_params[2] = sc.scan.Omega
+        if self.traj is not None:
+            d.traj = self.traj.data_ptr()
+        if pwv is not None:
+            d.pwv = pwv.data_ptr()
+            d.pwv_ld = pwv.shape[1]
+            d.pwv_len = pwv.shape[1]
+        if t_star is not None:
+            d.t_star = t_star.data_ptr()
+        if maps is not None:
+            d.map, d.weight = maps[0].data_ptr(), maps[1].data_ptr()
+            d.map_n = map_n
+            d.map_half_rad = map_half_rad
+        return d
+
+    def pink_job(self, tod, accumulate=True, kelvin=False) -> _abi.Job:
         sc = self.sc
         return _abi.Job(kind=JOB_PINK, spec_id=self.spec_id, n_pix=sc.n_pix,
                         t_total=sc.t_total, seed=sc.seed,
-                        flags=JOB_ACCUMULATE if accumulate else 0,
+                        flags=(JOB_ACCUMULATE if accumulate else 0)
+                        | (JOB_KELVIN if kelvin else 0),
                         pink_alpha=self.alpha.ctypes.data,
                         pink_knee_hz=sc.pink_knee_hz, tod=tod.data_ptr())

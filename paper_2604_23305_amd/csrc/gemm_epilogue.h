@@ -57,17 +57,22 @@ __device__ __forceinline__ void contraction_epilogue(
         if (ch >= a.K) break;
         // P_KID = c0 + C0 2^-p; NEP^2 = c1 + (C1 + C2 2^-p) 2^-p, in FP64
         // because 2^-2p lies below the FP32 normal range
-        const float pk = (float)(a.c0[ch] + (double)spk[chl * kEpiPitch + c] * a.pinv);
+        const double pkd = a.c0[ch] + (double)spk[chl * kEpiPitch + c] * a.pinv;
+        const float pk = (float)pkd;
         const double n2 = a.c1[ch] + (double)sn2[chl * kEpiPitch + c] * a.pinv;
         const float sg = (float)sqrt(fmax(n2, 0.0) * (double)a.fs_half);
-        float v = pk;
+        float wn = 0.f;
         if (a.photon) {
-          const u32x4 o = philox10(u32x4{(uint32_t)t, (uint32_t)ch, (uint32_t)p, 0u},
+          const u32x4 o = philox10(u32x4{(uint32_t)t, (uint32_t)ch, (uint32_t)(a.pix0 + p), 0u},
                                    a.key0, a.key1);
           float zc, zs;
           box_muller(o.x, o.y, &zc, &zs);
-          v += sg * zc;
+          wn = sg * zc;
         }
+        // Kelvin: (P - a_k) / b_k with the offset taken in FP64
+        const float v = a.kelvin
+            ? (float)(((pkd - a.kel_a[ch]) + (double)wn) * a.kel_ib[ch])
+            : pk + wn;
         const int64_t off = ((int64_t)p * a.K + ch) * a.out_ld + (t - a.out_t0);
         if (a.accumulate) a.tod[off] += v; else a.tod[off] = v;
         if (a.p_kid) a.p_kid[off] = pk;

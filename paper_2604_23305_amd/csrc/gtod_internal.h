@@ -69,7 +69,12 @@ struct GemmArgs {
   double pinv;
   float pinv_f;
   uint32_t key0, key1;
+  int pix0;              // noise-key index of the job's pixel 0
   int photon, accumulate;
+  // brightness-temperature output: tod = (P - kel_a) * kel_ib per channel
+  int kelvin;
+  const double* kel_a;   // [K]
+  const double* kel_ib;  // [K]
   float* tod;
   float* p_kid;
   float* sigma;
@@ -86,6 +91,7 @@ struct PinkArgs {
   const float* scale;    // [K] sqrt(A_k N fs / 4) / N
   const float* alpha;    // [K]
   uint32_t key0, key1;
+  int pix0;              // noise-key index of the job's pixel 0
   float* tod;
   int64_t t_total, out_ld;
   int accumulate;
@@ -108,8 +114,11 @@ struct SpecSetupArgs {
   double ref_pwv, pwv0, dpwv, ref_el;
   // outputs
   float* tau; float* E; float* D; float* W; float* Pref;
+  double* tau64;            // [n_pwv][F] zenith optical depth, FP64
+  double* E64; double* D64; // [F] cascade terms, FP64, unscaled
   double* Pref64;           // [Fp] the FP32 reference widened (exact)
-  double* B64;              // [3][F][K] scratch (B0, B1, B2)
+  double* B0_64;            // [F][K] B0 = w eta, FP64
+  double* B64;              // [2][F][K] scratch (B1, B2)
   float* B;                 // [3][Kp][Fp]
   uint16_t* Bh; uint16_t* Bl;
   double* c0; double* c1;   // [Kp]
@@ -129,6 +138,79 @@ struct PassTable {
   const double* pool;
 };
 
+// Skydip (brightness-temperature scale): a sweep of n zenith PWV values at
+// one elevation, no source.
+struct SkydipArgs {
+  int F, K, n_pwv, n;
+  double pwv_lo, pwv_hi, pwv0, dpwv, csc, t_atm;
+  const double* tau64;   // [n_pwv][F]
+  const double* E64;     // [F]
+  const double* D64;     // [F]
+  const double* B0;      // [F][K]
+  double* Pm;            // [n][F] scratch: spectral power of each sweep row
+  double* Xm;            // [n][F] scratch: sky emissivity 1 - eta_atm
+  double* p_kid;         // [n][K]
+  double* t_b;           // [n][K]
+  double* a;             // [K] intercept
+  double* b;             // [K] slope
+  double* ib;            // [K] 1 / slope
+};
+
+void launch_skydip(const SkydipArgs& a, hipStream_t s);
+
+// Common-mode subtraction and gridding of a Kelvin TOD (one channel group
+// [k0, k0 + kg) per launch of the group kernels).
+constexpr int kMaxMapN = 48;
+struct ReduceArgs {
+  int P, K, F, n_pwv;
+  int64_t T, t0, ld;          // the TOD holds samples [t0, t0 + T), stride ld
+  int k0, kg;
+  int scan_kind;
+  double r_petal, omega, Omega, f_s, theta0;
+  const double* traj;         // [t_total][2]
+  const double* dphi;         // [P] device (staged)
+  const double* dtheta;       // [P]
+  const int* off;             // [P] 1 if the spaxel is off source
+  int n_out;
+  const double* tau64;        // [n_pwv][F]
+  const double* B0;           // [F][K]
+  double pwv0, dpwv;
+  const float* pwv;           // [P][pwv_ld] zenith PWV output, or null
+  int64_t pwv_ld, pwv_len;
+  double pwv_host;            // used when pwv is null
+  double* pwv_mean;           // scratch [1]
+  double* lnz;                // scratch [K] ln of the channel zenith transmission
+  double2* scan_tab;          // scratch [T] (phi, theta)
+  const float* tod;           // [P][K][ld] brightness temperature
+  float* t_star;              // [P][K][ld] or null
+  double* M;                  // scratch [kg][T] common-mode term
+  int map_n;                  // 0: no maps
+  double half, dcell;
+  double2* stats;             // scratch [P][kg][C] (weight, mean)
+  double* map;                // [K][C]
+  double* weight;             // [K][C]
+};
+
+// Context services for library parts outside the runtime file: device
+// memory charged to the context's budget, the error message, and a few
+// properties.  (The context type is defined by the runtime.)
+}  // namespace gtod
+struct gtod_ctx;
+namespace gtod {
+int32_t ctx_alloc(gtod_ctx* c, void** p, size_t bytes);
+void ctx_free(gtod_ctx* c, void* p);
+int32_t ctx_fail(gtod_ctx* c, int32_t status, const char* msg);
+int ctx_device(const gtod_ctx* c);
+double ctx_f_sample(const gtod_ctx* c);
+int ctx_spec_channels(const gtod_ctx* c, int32_t spec_id);  // -1 if unknown
+// Two library-owned streams (default priority) kept until the context is
+// freed; null if creation failed.
+hipStream_t ctx_sink_stream(gtod_ctx* c, int which);
+
+void launch_reduce_setup(const ReduceArgs& a, hipStream_t s);
+void launch_reduce_common(const ReduceArgs& a, hipStream_t s);
+void launch_reduce_grid(const ReduceArgs& a, hipStream_t s);
+void launch_reduce_combine(const ReduceArgs& a, hipStream_t s);
 void launch_spec_setup(const SpecSetupArgs& a, const PassTable& pt,
                        hipStream_t s);
 void launch_scale_spectra(float* E, float* D, float* W, float* Pref, int Fp,

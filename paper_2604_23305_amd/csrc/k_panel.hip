@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "gtod_internal.h"
+#include "scan.h"
 
 namespace gtod {
 
@@ -57,15 +58,9 @@ __global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
       const int p = a.p0 + pl;
       const int64_t n = a.t0 + tl;
       const double t = (double)n / a.f_s;
-      double phi = 0.0, th = 0.0;
-      if (a.scan_kind == 1) {
-        const double sw = sin(a.omega * t);
-        phi = a.r_petal * cos(a.Omega * t) * sw;
-        th = a.r_petal * sin(a.Omega * t) * sw;
-      } else if (a.scan_kind == 2) {
-        phi = a.traj[2 * n];
-        th = a.traj[2 * n + 1];
-      }
+      double phi, th;
+      scan_offsets(a.scan_kind, a.r_petal, a.omega, a.Omega, a.traj, n, a.f_s,
+                   &phi, &th);
       const double x = a.h * tan(phi + a.dphi[p]) + a.wind * t;
       const double y = a.h * tan(th + a.dtheta[p]);
       int64_t cx, cy;

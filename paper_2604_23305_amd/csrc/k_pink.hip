@@ -139,7 +139,7 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
     const int64_t j = col[c] + (int64_t)M1 * k2;
     float2 x = make_float2(0.f, 0.f);
     if (j > 0 && j < a.M) {
-      const u32x4 o = philox10(u32x4{(uint32_t)j, (uint32_t)k, (uint32_t)p, 1u},
+      const u32x4 o = philox10(u32x4{(uint32_t)j, (uint32_t)k, (uint32_t)(a.pix0 + p), 1u},
                                a.key0, a.key1);
       float zc, zs;
       box_muller(o.x, o.y, &zc, &zs);

@@ -1,0 +1,220 @@
+// Common-mode atmosphere subtraction (section 4.3, Eqs. common_mode and
+// Sj) and inverse-variance gridding of a brightness-temperature TOD, FP64
+// arithmetic on FP32 data.
+//
+//   eta_z,k   = sum_j B0_jk eta_z,j(PWV_mean) / sum_j B0_jk
+//   eta_i     = eta_z,k ^ (1 / sin(theta(t) + theta0 + dtheta_i))
+//   M(t, k)   = (1 / N_out) sum_{j off source} T_b,j / (1 - eta_j)
+//   T*_i      = T_b,i / eta_i - (1 - eta_i) / eta_i M(t, k)
+// with 1 - eta = -expm1(ln eta) so that transparent channels keep their
+// relative precision.  Gridding bins T*_i(t, k) of spaxel i at (phi(t) +
+// dphi_i, theta(t) + dtheta_i) to the nearest node of an n x n grid; per
+// (spaxel, channel, cell) the mean and the variance of the samples give a
+// weight m / s^2, and the cells of all spaxels are combined with it.
+//
+// Kernels: setup (scan table, mean PWV, channel transmission), common (one
+// thread per (t, k): M and optionally T*), grid (one block per (spaxel,
+// channel): cell sums in LDS), combine (one thread per (channel, cell)).
+// The common and grid kernels each stream the TOD once: HBM-bound, with
+// the FP64 transcendental work per sample (one sine, exp, expm1) alongside.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "gtod_internal.h"
+#include "scan.h"
+
+namespace gtod {
+
+namespace {
+
+constexpr int kRdThreads = 256;
+
+__device__ double block_sum_256(double v, double* s) {
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int st = kRdThreads / 2; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) s[threadIdx.x] += s[threadIdx.x + st];
+    __syncthreads();
+  }
+  const double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ inline int map_cell(const ReduceArgs& a, double x, double y) {
+  const double gx = floor((x + a.half) / a.dcell + 0.5);
+  const double gy = floor((y + a.half) / a.dcell + 0.5);
+  if (!(gx >= 0.0 && gx < (double)a.map_n && gy >= 0.0 && gy < (double)a.map_n))
+    return -1;
+  return (int)gy * a.map_n + (int)gx;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(kRdThreads) void k_rd_scan(ReduceArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * kRdThreads + threadIdx.x;
+  if (t >= a.T) return;
+  double phi, th;
+  scan_offsets(a.scan_kind, a.r_petal, a.omega, a.Omega, a.traj, a.t0 + t,
+               a.f_s, &phi, &th);
+  a.scan_tab[t] = make_double2(phi, th);
+}
+
+// Mean zenith PWV (one block, fixed-order sums), then ln eta_z,k (one
+// block per channel).
+__global__ __launch_bounds__(kRdThreads) void k_rd_pwv_mean(ReduceArgs a) {
+  __shared__ double s[kRdThreads];
+  double acc = 0.0;
+  if (a.pwv) {
+    const int64_t n = (int64_t)a.P * a.pwv_len;
+    for (int64_t i = threadIdx.x; i < n; i += kRdThreads) {
+      const int64_t p = i / a.pwv_len, t = i % a.pwv_len;
+      acc += (double)a.pwv[p * a.pwv_ld + t];
+    }
+  }
+  const double tot = block_sum_256(acc, s);
+  if (threadIdx.x == 0)
+    a.pwv_mean[0] = a.pwv ? tot / ((double)a.P * (double)a.pwv_len) : a.pwv_host;
+}
+
+__global__ __launch_bounds__(kRdThreads) void k_rd_channel(ReduceArgs a) {
+  __shared__ double s[kRdThreads];
+  const int k = blockIdx.x;
+  double g = (a.pwv_mean[0] - a.pwv0) / a.dpwv;
+  g = fmin(fmax(g, 0.0), (double)(a.n_pwv - 1));
+  int ci = (int)floor(g);
+  if (ci > a.n_pwv - 2) ci = a.n_pwv - 2;
+  const double wg = g - ci;
+  double num = 0.0, den = 0.0;
+  for (int j = threadIdx.x; j < a.F; j += kRdThreads) {
+    const double tz = (1.0 - wg) * a.tau64[(int64_t)ci * a.F + j] +
+                      wg * a.tau64[(int64_t)(ci + 1) * a.F + j];
+    const double b = a.B0[(int64_t)j * a.K + k];
+    num += b * exp(-tz);
+    den += b;
+  }
+  const double N = block_sum_256(num, s);
+  const double D = block_sum_256(den, s);
+  if (threadIdx.x == 0) a.lnz[k] = (D > 0.0) ? log(N / D) : NAN;
+}
+
+__global__ __launch_bounds__(kRdThreads) void k_rd_common(ReduceArgs a) {
+  const int64_t t = (int64_t)blockIdx.x * kRdThreads + threadIdx.x;
+  const int kl = blockIdx.y;
+  if (t >= a.T) return;
+  const int k = a.k0 + kl;
+  const double lz = a.lnz[k];
+  const double th = a.scan_tab[t].y + a.theta0;
+  double sum = 0.0;
+  for (int p = 0; p < a.P; ++p) {
+    if (!a.off[p]) continue;
+    const double l = lz / sin(th + a.dtheta[p]);
+    sum += (double)a.tod[((int64_t)p * a.K + k) * a.ld + t] / -expm1(l);
+  }
+  const double M = sum / (double)a.n_out;
+  if (a.M) a.M[(int64_t)kl * a.T + t] = M;
+  if (!a.t_star) return;
+  for (int p = 0; p < a.P; ++p) {
+    const double l = lz / sin(th + a.dtheta[p]);
+    const double eta = exp(l);
+    const int64_t o = ((int64_t)p * a.K + k) * a.ld + t;
+    a.t_star[o] = (float)(((double)a.tod[o] + expm1(l) * M) / eta);
+  }
+}
+
+// One block per (spaxel, channel of the group), spaxel fastest so that the
+// blocks sharing a channel's M row run together.  Cell sums of v = T* -
+// shift (shift = the block's first sample) in LDS; the variance is
+// (S2 - S1^2 / m) / (m - 1).
+__global__ __launch_bounds__(kRdThreads) void k_rd_grid(ReduceArgs a) {
+  __shared__ unsigned cnt[kMaxMapN * kMaxMapN];
+  __shared__ double s1[kMaxMapN * kMaxMapN];
+  __shared__ double s2[kMaxMapN * kMaxMapN];
+  const int p = blockIdx.x % a.P;
+  const int kl = blockIdx.x / a.P;
+  const int k = a.k0 + kl;
+  const int C = a.map_n * a.map_n;
+  for (int c = threadIdx.x; c < C; c += kRdThreads) {
+    cnt[c] = 0u;
+    s1[c] = 0.0;
+    s2[c] = 0.0;
+  }
+  const double lz = a.lnz[k];
+  const double dth = a.theta0 + a.dtheta[p];
+  const double dph = a.dphi[p];
+  const float* row = a.tod + ((int64_t)p * a.K + k) * a.ld;
+  const double* Mr = a.M + (int64_t)kl * a.T;
+  auto tstar = [&](int64_t t, double th) {
+    const double l = lz / sin(th + dth);
+    return ((double)row[t] + expm1(l) * Mr[t]) / exp(l);
+  };
+  const double shift = tstar(0, a.scan_tab[0].y);
+  __syncthreads();
+  for (int64_t t = threadIdx.x; t < a.T; t += kRdThreads) {
+    const double2 sc = a.scan_tab[t];
+    const int c = map_cell(a, sc.x + dph, sc.y + a.dtheta[p]);
+    if (c < 0) continue;
+    const double v = tstar(t, sc.y) - shift;
+    atomicAdd(&cnt[c], 1u);
+    atomicAdd(&s1[c], v);
+    atomicAdd(&s2[c], v * v);
+  }
+  __syncthreads();
+  double2* out = a.stats + ((int64_t)p * a.kg + kl) * C;
+  for (int c = threadIdx.x; c < C; c += kRdThreads) {
+    const double m = (double)cnt[c];
+    double w = 0.0, mean = 0.0;
+    if (m >= 2.0) {
+      const double var = (s2[c] - s1[c] * s1[c] / m) / (m - 1.0);
+      if (var > 0.0) {
+        w = m / var;
+        mean = s1[c] / m + shift;
+      }
+    }
+    out[c] = make_double2(w, mean);
+  }
+}
+
+__global__ __launch_bounds__(kRdThreads) void k_rd_combine(ReduceArgs a) {
+  const int C = a.map_n * a.map_n;
+  const int c = blockIdx.x * kRdThreads + threadIdx.x;
+  const int kl = blockIdx.y;
+  if (c >= C) return;
+  double ws = 0.0, num = 0.0;
+  for (int p = 0; p < a.P; ++p) {
+    const double2 st = a.stats[((int64_t)p * a.kg + kl) * C + c];
+    if (st.x > 0.0) {
+      ws += st.x;
+      num += st.x * st.y;
+    }
+  }
+  const int64_t o = (int64_t)(a.k0 + kl) * C + c;
+  a.map[o] = ws > 0.0 ? num / ws : NAN;
+  a.weight[o] = ws;
+}
+
+void launch_reduce_setup(const ReduceArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rd_scan, dim3((unsigned)((a.T + kRdThreads - 1) / kRdThreads)),
+                     dim3(kRdThreads), 0, s, a);
+  hipLaunchKernelGGL(k_rd_pwv_mean, dim3(1), dim3(kRdThreads), 0, s, a);
+  hipLaunchKernelGGL(k_rd_channel, dim3(a.K), dim3(kRdThreads), 0, s, a);
+}
+
+void launch_reduce_common(const ReduceArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rd_common,
+                     dim3((unsigned)((a.T + kRdThreads - 1) / kRdThreads), a.kg),
+                     dim3(kRdThreads), 0, s, a);
+}
+
+void launch_reduce_grid(const ReduceArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_rd_grid, dim3((unsigned)(a.P * a.kg)), dim3(kRdThreads), 0, s, a);
+}
+
+void launch_reduce_combine(const ReduceArgs& a, hipStream_t s) {
+  const int C = a.map_n * a.map_n;
+  hipLaunchKernelGGL(k_rd_combine, dim3((C + kRdThreads - 1) / kRdThreads, a.kg),
+                     dim3(kRdThreads), 0, s, a);
+}
+
+}  // namespace gtod

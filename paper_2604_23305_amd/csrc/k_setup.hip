@@ -99,8 +99,13 @@ __global__ void k_spectral(SpecSetupArgs a, PassTable pt) {
     }
     W = e * W;
   }
-  for (int i = 0; i < a.n_pwv; ++i)
-    a.tau[(int64_t)i * a.Fp + j] = (float)(-log(a.eta_z[(int64_t)i * a.F + j]));
+  for (int i = 0; i < a.n_pwv; ++i) {
+    const double t = -log(a.eta_z[(int64_t)i * a.F + j]);
+    a.tau[(int64_t)i * a.Fp + j] = (float)t;
+    a.tau64[(int64_t)i * a.F + j] = t;
+  }
+  a.E64[j] = E;
+  a.D64[j] = D;
   // reference spectrum: zenith PWV ref_pwv, cosecant ref_csc, no source
   double g = (a.ref_pwv - a.pwv0) / a.dpwv;
   g = fmin(fmax(g, 0.0), (double)(a.n_pwv - 1));
@@ -148,9 +153,9 @@ __global__ void k_filters(SpecSetupArgs a) {
     const double b1 = 2.0 * w * eta * (hv + gap);
     const double b2 = 2.0 * w * eta * eta;
     const int64_t FK = (int64_t)a.F * a.K;
-    a.B64[(int64_t)j * a.K + k] = b0;
-    a.B64[FK + (int64_t)j * a.K + k] = b1;
-    a.B64[2 * FK + (int64_t)j * a.K + k] = b2;
+    a.B0_64[(int64_t)j * a.K + k] = b0;
+    a.B64[(int64_t)j * a.K + k] = b1;
+    a.B64[FK + (int64_t)j * a.K + k] = b2;
     const int64_t KF = (int64_t)a.Kp * a.Fp;
     const float v[3] = {(float)b0, (float)(b1 + 2.0 * pr * b2), (float)b2};
     for (int m = 0; m < 3; ++m) {
@@ -174,8 +179,8 @@ __global__ __launch_bounds__(256) void k_reference(SpecSetupArgs a) {
     for (int j = threadIdx.x; j < a.F; j += 256) {
       const double p = a.Pref64[j];
       const int64_t o = (int64_t)j * a.K + k;
-      acc0 += p * a.B64[o];
-      acc1 += p * a.B64[FK + o] + p * p * a.B64[2 * FK + o];
+      acc0 += p * a.B0_64[o];
+      acc1 += p * a.B64[o] + p * p * a.B64[FK + o];
     }
   }
   s0[threadIdx.x] = acc0;

@@ -42,6 +42,17 @@ struct SpecObj {
   double* c1 = nullptr;
   int pexp = 0;   // the panel carries spectral powers times 2^pexp
   std::vector<double> nep2ref;
+  // FP64 tables kept for the skydip, and its brightness-temperature scale
+  double t_atm = 0;
+  double* tau64 = nullptr;
+  double* E64 = nullptr;
+  double* D64 = nullptr;
+  double* B0_64 = nullptr;
+  double* kel_a = nullptr;
+  double* kel_b = nullptr;
+  double* kel_ib = nullptr;
+  bool has_kelvin = false;
+  std::vector<double> kel_ib_h;
   std::vector<void*> allocs;
 };
 
@@ -76,6 +87,7 @@ struct gtod_ctx {
   std::map<void*, size_t> sizes;
   std::map<hipStream_t, StreamWs> ws;
   unsigned long long* counters = nullptr;
+  hipStream_t sink_streams[2] = {nullptr, nullptr};  // out-of-core runs
   std::string err;
   // profiling
   bool prof = false;
@@ -244,11 +256,16 @@ gtod_status validate(gtod_ctx* c, const gtod_job& j, int idx, JobPlan* pl) {
   pl->spec = &sp->second;
   pl->scr = nullptr;
   if (j.n_pix < 1) return fail(c, GTOD_EINVAL, at + "n_pix < 1");
+  if (j.pix0 < 0 || (int64_t)j.pix0 + j.n_pix > ((int64_t)1 << 31))
+    return fail(c, GTOD_EINVAL, at + "pix0 out of range");
   if (!j.tod) return fail(c, GTOD_EINVAL, at + "tod is NULL");
   if (j.t_total < 1 || j.t_total > (int64_t)1 << 31)
     return fail(c, GTOD_EINVAL, at + "t_total out of range");
-  if (j.flags & ~(GTOD_JOB_PHOTON_NOISE | GTOD_JOB_ACCUMULATE))
+  if (j.flags & ~(GTOD_JOB_PHOTON_NOISE | GTOD_JOB_ACCUMULATE | GTOD_JOB_KELVIN))
     return fail(c, GTOD_EINVAL, at + "unknown flags");
+  if ((j.flags & GTOD_JOB_KELVIN) && !pl->spec->has_kelvin)
+    return fail(c, GTOD_EINVAL, at + "KELVIN output needs a brightness scale: "
+                                     "run gtod_skydip on this spectral setup first");
   const int64_t ot0 = j.out_ld ? j.out_t0 : 0, old = j.out_ld ? j.out_ld : j.t_total;
   if (old < 1 || ot0 < 0) return fail(c, GTOD_EINVAL, at + "bad output window");
   if (j.kind == GTOD_JOB_PINK && (ot0 != 0 || old < j.t_total))
@@ -321,6 +338,29 @@ gtod_status validate(gtod_ctx* c, const gtod_job& j, int idx, JobPlan* pl) {
 }
 
 }  // namespace
+
+namespace gtod {
+
+int32_t ctx_alloc(gtod_ctx* c, void** p, size_t bytes) { return dev_alloc(c, p, bytes); }
+void ctx_free(gtod_ctx* c, void* p) { dev_free(c, p); }
+int32_t ctx_fail(gtod_ctx* c, int32_t status, const char* msg) { return fail(c, status, msg); }
+int ctx_device(const gtod_ctx* c) { return c->device; }
+double ctx_f_sample(const gtod_ctx* c) { return c->fs; }
+hipStream_t ctx_sink_stream(gtod_ctx* c, int which) {
+  hipStream_t& s = c->sink_streams[which & 1];
+  if (!s && hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipGetLastError();
+    s = nullptr;
+  }
+  return s;
+}
+
+int ctx_spec_channels(const gtod_ctx* c, int32_t spec_id) {
+  auto it = c->specs.find(spec_id);
+  return it == c->specs.end() ? -1 : it->second.K;
+}
+
+}  // namespace gtod
 
 extern "C" {
 
@@ -496,6 +536,7 @@ gtod_status gtod_load_filters(gtod_ctx* c, const gtod_spectral_desc* d, int32_t*
   so.n_pwv = d->n_pwv;
   so.pwv0 = d->pwv0_mm;
   so.dpwv = d->dpwv_mm;
+  so.t_atm = d->t_atm_K;
   const int64_t Fp = so.Fp, Kp = so.Kp;
   gtod_status st = GTOD_OK;
   auto res = [&](void** p, size_t bytes) {
@@ -513,6 +554,10 @@ gtod_status gtod_load_filters(gtod_ctx* c, const gtod_spectral_desc* d, int32_t*
   res((void**)&so.Bl, 3 * Kp * Fp * 2);
   res((void**)&so.c0, Kp * 8);
   res((void**)&so.c1, Kp * 8);
+  res((void**)&so.tau64, (size_t)d->n_pwv * F * 8);
+  res((void**)&so.E64, F * 8);
+  res((void**)&so.D64, F * 8);
+  res((void**)&so.B0_64, (size_t)F * K * 8);
   // temporaries
   std::vector<void*> tmp;
   auto tmpa = [&](void** p, size_t bytes) {
@@ -534,7 +579,7 @@ gtod_status gtod_load_filters(gtod_ctx* c, const gtod_spectral_desc* d, int32_t*
   tmpa((void**)&d_off, std::max<size_t>(poff.size(), 1) * 4);
   tmpa((void**)&d_order, K * 4);
   tmpa((void**)&d_pref64, Fp * 8);
-  tmpa((void**)&d_B64, (size_t)3 * F * K * 8);
+  tmpa((void**)&d_B64, (size_t)2 * F * K * 8);
   if (d->filter_mode == GTOD_FILT_MATRIX) {
     tmpa((void**)&d_mat, (size_t)F * K * 8);
   } else {
@@ -606,7 +651,11 @@ gtod_status gtod_load_filters(gtod_ctx* c, const gtod_spectral_desc* d, int32_t*
     a.D = so.D;
     a.W = so.W;
     a.Pref = so.Pref;
+    a.tau64 = so.tau64;
+    a.E64 = so.E64;
+    a.D64 = so.D64;
     a.Pref64 = d_pref64;
+    a.B0_64 = so.B0_64;
     a.B64 = d_B64;
     a.B = so.B;
     a.Bh = so.Bh;
@@ -695,9 +744,12 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
       const int64_t N = [&] { int64_t n = 2; while (n < j.t_total) n *= 2; return n; }();
       float* scale = (float*)(hs + plan[i].off_scale);
       float* alpha = (float*)(hs + plan[i].off_alpha);
+      const bool kel = (j.flags & GTOD_JOB_KELVIN) != 0;
       for (int k = 0; k < f.K; ++k) {
         const double A = f.nep2ref[k] * std::pow(j.pink_knee_hz, j.pink_alpha[k]);
-        scale[k] = (float)(std::sqrt(A * (double)N * c->fs / 4.0) / (double)N);
+        double sc = std::sqrt(A * (double)N * c->fs / 4.0) / (double)N;
+        if (kel) sc *= f.kel_ib_h[k];
+        scale[k] = (float)sc;
         alpha[k] = (float)j.pink_alpha[k];
       }
     }
@@ -728,6 +780,7 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
       a.alpha = (const float*)(ds + plan[i].off_alpha);
       a.key0 = key0;
       a.key1 = key1;
+      a.pix0 = j.pix0;
       a.tod = j.tod;
       a.t_total = j.t_total;
       a.out_ld = j.out_ld ? j.out_ld : j.t_total;
@@ -823,8 +876,12 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
     ga.pinv_f = std::ldexp(1.0f, -f.pexp);
     ga.key0 = key0;
     ga.key1 = key1;
+    ga.pix0 = j.pix0;
     ga.photon = (j.flags & GTOD_JOB_PHOTON_NOISE) != 0;
     ga.accumulate = acc;
+    ga.kelvin = (j.flags & GTOD_JOB_KELVIN) != 0;
+    ga.kel_a = f.kel_a;
+    ga.kel_ib = f.kel_ib;
     ga.tod = j.tod;
     ga.p_kid = j.p_kid;
     ga.sigma = j.sigma;
@@ -862,6 +919,213 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
   return GTOD_OK;
 }
 
+gtod_status gtod_skydip(gtod_ctx* c, int32_t spec_id, double el_rad, double pwv_lo_mm,
+                        double pwv_hi_mm, int32_t n, double* a_out, double* b_out,
+                        double* p_kid_out, double* t_b_out) {
+  if (!c) return GTOD_EINVAL;
+  auto it = c->specs.find(spec_id);
+  if (it == c->specs.end()) return fail(c, GTOD_ENOTFOUND, "unknown spec id");
+  SpecObj& f = it->second;
+  if (!(el_rad > 0.0 && el_rad < M_PI)) return fail(c, GTOD_EINVAL, "el_rad outside (0, pi)");
+  if (!std::isfinite(pwv_lo_mm) || !std::isfinite(pwv_hi_mm) || !(pwv_hi_mm > pwv_lo_mm))
+    return fail(c, GTOD_EINVAL, "need finite pwv_lo_mm < pwv_hi_mm");
+  if (n < 2 || n > GTOD_SKYDIP_MAX_N) return fail(c, GTOD_EINVAL, "n outside [2, GTOD_SKYDIP_MAX_N]");
+  const double top = f.pwv0 + (f.n_pwv - 1) * f.dpwv;
+  if ((c->flags & GTOD_INIT_STRICT_RANGE) && (pwv_lo_mm < f.pwv0 || pwv_hi_mm > top))
+    return fail(c, GTOD_ERANGE, "skydip PWV range leaves the transmission table");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipDeviceSynchronize());
+  gtod_status st = GTOD_OK;
+  if (!f.kel_a) {
+    auto res = [&](double** p) {
+      if (st != GTOD_OK) return;
+      st = dev_alloc(c, (void**)p, (size_t)f.Kp * 8);
+      if (st == GTOD_OK) f.allocs.push_back(*p);
+    };
+    res(&f.kel_a);
+    res(&f.kel_b);
+    res(&f.kel_ib);
+    if (st != GTOD_OK) return st;
+  }
+  double *Pm = nullptr, *Xm = nullptr, *pk = nullptr, *tb = nullptr;
+  const size_t nf = (size_t)n * f.F * 8, nk = (size_t)n * f.K * 8;
+  st = dev_alloc(c, (void**)&Pm, nf);
+  if (st == GTOD_OK) st = dev_alloc(c, (void**)&Xm, nf);
+  if (st == GTOD_OK) st = dev_alloc(c, (void**)&pk, nk);
+  if (st == GTOD_OK) st = dev_alloc(c, (void**)&tb, nk);
+  auto cleanup = [&] {
+    dev_free(c, Pm);
+    dev_free(c, Xm);
+    dev_free(c, pk);
+    dev_free(c, tb);
+  };
+  if (st != GTOD_OK) {
+    cleanup();
+    return st;
+  }
+  SkydipArgs a{};
+  a.F = f.F;
+  a.K = f.K;
+  a.n_pwv = f.n_pwv;
+  a.n = n;
+  a.pwv_lo = pwv_lo_mm;
+  a.pwv_hi = pwv_hi_mm;
+  a.pwv0 = f.pwv0;
+  a.dpwv = f.dpwv;
+  a.csc = 1.0 / std::sin(el_rad);
+  a.t_atm = f.t_atm;
+  a.tau64 = f.tau64;
+  a.E64 = f.E64;
+  a.D64 = f.D64;
+  a.B0 = f.B0_64;
+  a.Pm = Pm;
+  a.Xm = Xm;
+  a.p_kid = pk;
+  a.t_b = tb;
+  a.a = f.kel_a;
+  a.b = f.kel_b;
+  a.ib = f.kel_ib;
+  launch_skydip(a, nullptr);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  std::vector<double> ib(f.K);
+  if (e == hipSuccess) e = hipMemcpy(ib.data(), f.kel_ib, f.K * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && a_out) e = hipMemcpy(a_out, f.kel_a, f.K * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && b_out) e = hipMemcpy(b_out, f.kel_b, f.K * 8, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && p_kid_out) e = hipMemcpy(p_kid_out, pk, nk, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && t_b_out) e = hipMemcpy(t_b_out, tb, nk, hipMemcpyDeviceToHost);
+  cleanup();
+  if (e != hipSuccess) {
+    f.has_kelvin = false;
+    return fail(c, GTOD_EDEVICE, std::string("skydip: ") + hipGetErrorString(e));
+  }
+  f.kel_ib_h = ib;
+  f.has_kelvin = true;
+  return GTOD_OK;
+}
+
+gtod_status gtod_reduce(gtod_ctx* c, const gtod_reduce_desc* d, void* hip_stream) {
+  if (!c) return GTOD_EINVAL;
+  if (!d) return fail(c, GTOD_EINVAL, "NULL descriptor");
+  auto it = c->specs.find(d->spec_id);
+  if (it == c->specs.end()) return fail(c, GTOD_ENOTFOUND, "unknown spec id");
+  const SpecObj& f = it->second;
+  const int P = d->n_pix;
+  if (P < 1 || !d->dphi_rad || !d->dtheta_rad) return fail(c, GTOD_EINVAL, "need n_pix >= 1 and pixel offsets");
+  if (!d->tod) return fail(c, GTOD_EINVAL, "tod is NULL");
+  if (d->T < 1 || d->t0 < 0 || d->ld < d->T) return fail(c, GTOD_EINVAL, "bad sample window (T >= 1, t0 >= 0, ld >= T)");
+  if (d->scan_kind < 0 || d->scan_kind > 2) return fail(c, GTOD_EINVAL, "unknown scan kind");
+  if (d->scan_kind == GTOD_SCAN_TRAJ && (!d->traj || d->t0 + d->T > d->t_total))
+    return fail(c, GTOD_EINVAL, "TRAJ scan needs traj covering [t0, t0 + T)");
+  if (d->scan_kind == GTOD_SCAN_DAISY)
+    for (int q = 0; q < 3; ++q)
+      if (!std::isfinite(d->scan_params[q])) return fail(c, GTOD_EINVAL, "daisy parameters not finite");
+  if (!std::isfinite(d->theta0_rad)) return fail(c, GTOD_EINVAL, "theta0 not finite");
+  if (d->pwv ? (d->pwv_len < 1 || d->pwv_ld < d->pwv_len) : !std::isfinite(d->pwv_mean_mm))
+    return fail(c, GTOD_EINVAL, "need a PWV array (pwv_len >= 1, pwv_ld >= pwv_len) or a finite pwv_mean_mm");
+  if (!(d->r_out_rad >= 0.0) || !std::isfinite(d->r_out_rad)) return fail(c, GTOD_EINVAL, "r_out_rad must be finite and >= 0");
+  const bool maps = d->map || d->weight;
+  if (maps && (!d->map || !d->weight)) return fail(c, GTOD_EINVAL, "map and weight must both be set");
+  if (!maps && !d->t_star) return fail(c, GTOD_EINVAL, "no output: set t_star, or map and weight");
+  if (maps && (d->map_n < 2 || d->map_n > GTOD_MAP_MAX_N || !finite_pos(d->map_half_rad)))
+    return fail(c, GTOD_EINVAL, "map_n outside [2, GTOD_MAP_MAX_N] or map_half_rad <= 0");
+  std::vector<int> off(P);
+  int n_out = 0;
+  for (int p = 0; p < P; ++p) {
+    if (!std::isfinite(d->dphi_rad[p]) || !std::isfinite(d->dtheta_rad[p]))
+      return fail(c, GTOD_EINVAL, "pixel offsets not finite");
+    off[p] = std::hypot(d->dphi_rad[p], d->dtheta_rad[p]) > d->r_out_rad;
+    n_out += off[p];
+  }
+  if (n_out == 0) return fail(c, GTOD_EINVAL, "no spaxel lies outside r_out_rad");
+  const size_t stage_bytes = (size_t)P * 20 + 64;
+  if (stage_bytes > kSlotBytes) return fail(c, GTOD_EINVAL, "too many spaxels");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  StreamWs* w = nullptr;
+  gtod_status st = get_ws(c, s, &w);
+  if (st != GTOD_OK) return st;
+  // workspace: scan table, channel transmissions and mean PWV, then per
+  // channel group the common-mode rows and the cell statistics
+  const int64_t T = d->T, K = f.K;
+  const int64_t C = maps ? (int64_t)d->map_n * d->map_n : 0;
+  const int64_t fixed = round_up(T * 16, 256) + round_up(K * 8, 256) + 256;
+  const int64_t per_ch = maps ? round_up(T * 8, 256) + (int64_t)P * C * 16 : 0;
+  const int64_t avail = (int64_t)w->panel_bytes - fixed;
+  int64_t kg = avail > 0 ? K : 0;
+  if (maps) kg = avail > 0 ? std::min<int64_t>(K, (avail - 256) / per_ch) : 0;
+  if (kg < 1) return fail(c, GTOD_EINVAL, "workspace too small for one channel of the reduction");
+
+  const int slot = w->slot;
+  w->slot = (w->slot + 1) % kSlots;
+  if (w->ev_used[slot]) HIP_TRY(c, hipEventSynchronize(w->ev[slot]));
+  char* hs = w->h_stage + (size_t)slot * kSlotBytes;
+  char* ds = w->d_stage + (size_t)slot * kSlotBytes;
+  std::memcpy(hs, d->dphi_rad, (size_t)P * 8);
+  std::memcpy(hs + (size_t)P * 8, d->dtheta_rad, (size_t)P * 8);
+  std::memcpy(hs + (size_t)P * 16, off.data(), (size_t)P * 4);
+  HIP_TRY(c, hipMemcpyAsync(ds, hs, (size_t)P * 20, hipMemcpyHostToDevice, s));
+
+  char* ws = (char*)w->panel;
+  ReduceArgs a{};
+  a.P = P;
+  a.K = f.K;
+  a.F = f.F;
+  a.n_pwv = f.n_pwv;
+  a.T = T;
+  a.t0 = d->t0;
+  a.ld = d->ld;
+  a.scan_kind = d->scan_kind;
+  a.r_petal = d->scan_params[0];
+  a.omega = d->scan_params[1];
+  a.Omega = d->scan_params[2];
+  a.f_s = c->fs;
+  a.theta0 = d->theta0_rad;
+  a.traj = d->traj;
+  a.dphi = (const double*)ds;
+  a.dtheta = (const double*)(ds + (size_t)P * 8);
+  a.off = (const int*)(ds + (size_t)P * 16);
+  a.n_out = n_out;
+  a.tau64 = f.tau64;
+  a.B0 = f.B0_64;
+  a.pwv0 = f.pwv0;
+  a.dpwv = f.dpwv;
+  a.pwv = d->pwv;
+  a.pwv_ld = d->pwv_ld;
+  a.pwv_len = d->pwv_len;
+  a.pwv_host = d->pwv_mean_mm;
+  a.scan_tab = (double2*)ws;
+  a.lnz = (double*)(ws + round_up(T * 16, 256));
+  a.pwv_mean = (double*)(ws + round_up(T * 16, 256) + round_up(K * 8, 256));
+  a.tod = d->tod;
+  a.t_star = d->t_star;
+  a.map_n = maps ? d->map_n : 0;
+  a.half = d->map_half_rad;
+  a.dcell = maps ? 2.0 * d->map_half_rad / (d->map_n - 1) : 0.0;
+  a.map = d->map;
+  a.weight = d->weight;
+  char* grp = ws + fixed;
+  a.M = maps ? (double*)grp : nullptr;
+  a.stats = maps ? (double2*)(grp + round_up(kg * T * 8, 256)) : nullptr;
+  launch_reduce_setup(a, s);
+  for (int64_t k0 = 0; k0 < K; k0 += kg) {
+    a.k0 = (int)k0;
+    a.kg = (int)std::min<int64_t>(kg, K - k0);
+    const double samples = (double)P * a.kg * T;
+    const double cm_bytes = samples * (d->t_star ? 8.0 : 4.0) + (maps ? 8.0 * a.kg * T : 0.0);
+    timed(c, GTOD_KERNEL_COMMON, cm_bytes, s, [&] { launch_reduce_common(a, s); });
+    if (maps) {
+      const double gb = samples * 4.0 + 8.0 * a.kg * T + 16.0 * P * a.kg * C;
+      timed(c, GTOD_KERNEL_GRID, gb, s, [&] { launch_reduce_grid(a, s); });
+      launch_reduce_combine(a, s);
+    }
+  }
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipEventRecord(w->ev[slot], s));
+  w->ev_used[slot] = true;
+  return GTOD_OK;
+}
+
 gtod_status gtod_free(gtod_ctx* c, int32_t kind, int32_t id) {
   if (!c) return GTOD_EINVAL;
   (void)hipSetDevice(c->device);
@@ -888,6 +1152,8 @@ gtod_status gtod_free(gtod_ctx* c, int32_t kind, int32_t id) {
     for (auto& kv : c->screens) dev_free(c, kv.second.pwv);
     for (auto& kv : c->specs) free_spec(c, kv.second);
     for (auto& kv : c->ws) free_ws(c, kv.second);
+    for (hipStream_t s : c->sink_streams)
+      if (s) (void)hipStreamDestroy(s);
     dev_free(c, c->counters);
     delete c;
     return GTOD_OK;
@@ -962,12 +1228,13 @@ gtod_status gtod_profile_read(gtod_ctx* c, double* out, int32_t n_kernels) {
   return GTOD_OK;
 }
 
-void gtod_abi_sizes(int64_t out[5]) {
+void gtod_abi_sizes(int64_t out[6]) {
   out[0] = sizeof(gtod_init_desc);
   out[1] = sizeof(gtod_screen_desc);
   out[2] = sizeof(gtod_stage);
   out[3] = sizeof(gtod_spectral_desc);
   out[4] = sizeof(gtod_job);
+  out[5] = sizeof(gtod_reduce_desc);
 }
 
 }  // extern "C"

@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_struct_layouts_match_c():
     lib = _abi.load()
-    out = (ctypes.c_int64 * 5)()
+    out = (ctypes.c_int64 * 6)()
     lib.gtod_abi_sizes(out)
     assert list(out) == _abi.struct_sizes()
 
