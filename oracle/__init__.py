@@ -18,5 +18,6 @@ Modules
   pink     Timmer-Koenig 1/f series
   skydip   brightness-temperature scale by a simulated skydip
   reduce   common-mode atmosphere subtraction and inverse-variance gridding
+  inputs   aperture field, far field, source-beam and screen-footprint convolutions
 """
-from . import physics, filters, philox, tod, pink, skydip, reduce  # noqa: F401
+from . import physics, filters, philox, tod, pink, skydip, reduce, inputs  # noqa: F401,E501

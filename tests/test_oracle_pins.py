@@ -821,3 +821,77 @@ def test_inverse_variance_combination_closed_form():
     np.testing.assert_allclose(m[0, :2], [(4 * 1 + 3) / 5, (4 * 2 - 1) / 5])
     np.testing.assert_allclose(w[0, :2], [5.0, 5.0])
     assert m[0, 2] == 3.0 and w[0, 2] == 4.0
+
+
+# --------------------------------------------------------------------------
+# input preparation (section 2.2)
+# --------------------------------------------------------------------------
+def test_far_field_uniform_aperture_is_airy():
+    """No taper: the far field of a uniformly lit disc is the Airy pattern
+    [2 J1(x) / x]^2, x = 2 pi rho R / lambda."""
+    from scipy import special
+    from oracle import inputs as oin
+    nu, R = 300e9, 5.0
+    lam = 299792458.0 / nu
+    rho = np.array([0.0, 1e-6, 5 * gen.ARCSEC, 11 * gen.ARCSEC, 30 * gen.ARCSEC])
+    got = oin.far_field(rho, nu, R, 0.0)
+    x = 2 * np.pi * rho[1:] * R / lam
+    np.testing.assert_allclose(got[1:], (2 * special.j1(x) / x) ** 2,
+                               rtol=1e-9, atol=1e-14)
+    assert got[0] == pytest.approx(1.0, abs=1e-14)
+
+
+def test_far_field_taper_widens_the_beam():
+    from oracle import inputs as oin
+    rho = 15 * gen.ARCSEC
+    f0 = oin.far_field(rho, 350e9, 5.0, 0.0)
+    f10 = oin.far_field(rho, 350e9, 5.0, -10.0)
+    assert 0 < f0 < f10 < 1
+
+
+def test_source_convolution_of_a_single_node():
+    """A source in one grid node spreads as A_p I cos(theta') dphi dtheta
+    F(distance)."""
+    from oracle import inputs as oin
+    n, F = 5, 2
+    nu = np.array([250e9, 400e9])
+    d = 10 * gen.ARCSEC
+    el0 = 0.8
+    I = np.zeros((n, n, F))
+    I[1, 3, :] = [2e-18, 5e-18]
+    P = oin.convolve_source(I, nu, -2 * d, d, el0, d, 5.0, -10.0)
+    for f in range(F):
+        for j in range(n):
+            for i in range(n):
+                rho = np.hypot((i - 3) * d, (j - 1) * d)
+                exp = (np.pi * 25.0 * d * d * I[1, 3, f] * np.cos(el0 + d)
+                       * oin.far_field(rho, nu[f], 5.0, -10.0))
+                assert P[j, i, f] == pytest.approx(exp, rel=1e-12)
+
+
+def test_screen_footprint_constant_delta_and_edges():
+    """Constant screens are unchanged; a unit cell in the interior spreads
+    into the normalised weights; edges clamp (brute-force loops)."""
+    from oracle import inputs as oin
+    dx = dy = 0.5
+    R, te = 1.6, -12.0
+    w = oin.footprint_weights(dx, dy, R, te)
+    assert w.shape == (7, 7) and w.sum() == pytest.approx(1.0, rel=1e-15)
+    assert w[0, 0] == 0.0 and w[3, 3] == w.max()
+    np.testing.assert_allclose(oin.convolve_screen(np.full((9, 12), 0.7), dx,
+                                                   dy, R, te), 0.7, rtol=1e-14)
+    s = np.zeros((11, 13))
+    s[5, 6] = 1.0
+    out = oin.convolve_screen(s, dx, dy, R, te)
+    np.testing.assert_allclose(out[2:9, 3:10], w[::-1, ::-1], rtol=1e-14)
+    rng = np.random.default_rng(4)
+    s = rng.uniform(0.5, 1.5, (6, 8))
+    out = oin.convolve_screen(s, dx, dy, R, te)
+    for y in range(6):
+        for x in range(8):
+            acc = 0.0
+            for a in range(-3, 4):
+                for b in range(-3, 4):
+                    acc += w[a + 3, b + 3] * s[min(max(y + a, 0), 5),
+                                               min(max(x + b, 0), 7)]
+            assert out[y, x] == pytest.approx(acc, rel=1e-13)
