@@ -63,6 +63,11 @@ def parse():
                     help="output in kelvin: calibrate by an N-point skydip "
                          "(PWV 0.25-2.75 mm at the scan elevation) before "
                          "the timed steps")
+    ap.add_argument("--to-disk", default=None, metavar="DIR",
+                    help="instead of the in-HBM steps, time one out-of-core "
+                         "run (gtod_simulate_to_disk) of the workload cut "
+                         "to --disk-seconds, written to DIR (removed after)")
+    ap.add_argument("--disk-seconds", type=float, default=360.0)
     ap.add_argument("--reduce", action="store_true",
                     help="after the simulation steps, time gtod_reduce "
                          "(common-mode subtraction + 31x31 inverse-variance "
@@ -126,6 +131,44 @@ def cpu_baseline(sc, target_s):
                        f"{sc.t_total}-sample 1/f series "
                        f"({t_pink_series:.2f} s each), combined per "
                        f"detector-sample")}
+
+
+def run_to_disk(args, g, torch):
+    """One out-of-core run: pixel groups streamed device -> pinned host ->
+    .npy files; reports end-to-end detector-samples/s and bytes/s."""
+    import shutil
+    from workloads import configs
+    T = int(round(args.disk_seconds * configs.F_SAMPLE))
+    mk = {"c2": configs.c2, "c3": configs.c3, "c4": configs.c4}[args.workload]
+    sc = mk(t_total=T)
+    prec = g.PREC_SPLIT_BF16 if (args.precision or ("split" if args.workload
+                                                    == "c4" else "fp32")) \
+        == "split" else g.PREC_FP32
+    ctx = g.sim_init(device=0, precision=prec,
+                     workspace_bytes=int(args.workspace_gib * (1 << 30)))
+    run = g.ScenarioRun(ctx, sc)
+    dummy = g.Outputs(tod=torch.empty(1, device="cuda"), t0=0, length=T)
+    sig, pk = run.signal_job(dummy), run.pink_job(dummy.tod)
+    out_dir = os.path.join(args.to_disk, "gtod_sink_bench")
+    per_pix = sc.K * T * 4 + T * 4
+    dev = 2 * 7 * per_pix                      # two slabs of 7 pixels
+    res = {}
+    try:
+        wall, nbytes, groups, G = g.simulate_to_disk(
+            ctx, sig, pk, out_dir, device_bytes=dev, host_bytes=1 << 30)
+        det = sc.n_pix * sc.K * T
+        res = {"metric": "out-of-core detector-samples/s (device -> pinned "
+                         "host -> .npy files)",
+               "value": det / wall, "unit": "detector-samples/s",
+               "bytes_per_s": nbytes / wall, "bytes": nbytes,
+               "wall_s": wall, "groups": groups, "pixels_per_group": G,
+               "config": {"workload": f"{args.workload} cut to {T} samples",
+                          "dir": args.to_disk, "device_bytes": dev,
+                          "host_bytes": 1 << 30}}
+    finally:
+        shutil.rmtree(out_dir, ignore_errors=True)
+        g.free(ctx)
+    print(json.dumps(res), flush=True)
 
 
 def cpu_skydip(sc, n):
@@ -316,6 +359,9 @@ def main():
                 f"request {rep.name} ({rep.n_pix} px, {rep.K} ch, "
                 f"{rep.F} bins): " + res["cpu_baseline"]["sample"])
         print(json.dumps(res), flush=True)
+        return
+    if args.to_disk:
+        run_to_disk(args, g, torch)
         return
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

@@ -414,6 +414,62 @@ gtod_status gtod_simulate_to_disk(gtod_ctx* ctx, const gtod_job* signal,
                                   const gtod_job* pink,
                                   const gtod_sink_desc* sink, double* stats);
 
+/* ---- input preparation (section 2.2) ---------------------------------
+ * Aperture illumination (Eq. aper_dist, circularly symmetric Gaussian
+ * with edge taper t_edge_db, negative, at the rim): A(r) = 10^(t_edge_db
+ * (r / r_tel_m)^2 / 20) for r < r_tel_m, else 0.
+ */
+
+/*
+ * gtod_far_field -- peak-normalised far-field power pattern F = |FT{A}|^2
+ * (section 2.2), evaluated exactly for the circularly symmetric aperture as
+ * the square of its Hankel transform, H(rho) = int_0^R A(r) J0(2 pi rho r
+ * / lambda) r dr, over F frequencies nu_hz (host [F]) on the grid rho =
+ * sqrt((a da_rad)^2 + (b db_rad)^2), a < n_a, b < n_b.
+ * Output: out (device [F][n_b][n_a], FP32).  Enqueued on hip_stream.
+ * Errors: EINVAL (sizes, spacings, r_tel_m <= 0, a grid too oscillatory
+ *   for the quadrature: 2 pi rho_max r_tel / lambda_min > 6000).
+ */
+gtod_status gtod_far_field(gtod_ctx* ctx, const double* nu_hz, int32_t F,
+                           int32_t n_a, int32_t n_b, double da_rad,
+                           double db_rad, double r_tel_m, double t_edge_db,
+                           float* out, void* hip_stream);
+
+/*
+ * gtod_convolve_source -- spectral source power from specific intensity
+ * (Eq. convolve_src): on the source grid az_i = az0 + i daz, el_j = el0 +
+ * j del (i < n_az, j < n_el),
+ *   P(i, j, f) = A_p daz del sum_{i', j'} I(i', j', f) cos(el_j')
+ *                F_f(sqrt(((i - i') daz)^2 + ((j - j') del)^2)),
+ * A_p = pi r_tel_m^2, F_f the far field above at nu_hz[f].
+ * in: device [n_el][n_az][ld_in] float (W m^-2 Hz^-1 sr^-1); out: device
+ *   [n_el][n_az][ld_out] float (W/Hz), the cube layout gtod_job takes;
+ *   in and out must not overlap.  n_az n_el <= 20000.
+ * Uses the stream's workspace for far-field tables (frequencies in
+ *   batches that fit).  Errors: EINVAL, EDEVICE.
+ */
+gtod_status gtod_convolve_source(gtod_ctx* ctx, const float* in,
+                                 int32_t n_az, int32_t n_el, int64_t ld_in,
+                                 const double* nu_hz, int32_t F,
+                                 double daz_rad, double el0_rad,
+                                 double del_rad, double r_tel_m,
+                                 double t_edge_db, float* out,
+                                 int64_t ld_out, void* hip_stream);
+
+/*
+ * gtod_convolve_screen -- line-of-sight PWV screen by the aperture
+ * footprint (section 2.2): each cell becomes the A-weighted mean of the
+ * cells whose centres lie within r_tel_m (weights A(r) normalised to 1;
+ * half widths floor(r_tel_m / dx_m) <= 32 and floor(r_tel_m / dy_m) <= 32
+ * cells), indices clamped at the screen edges.  in, out: device [ny][nx]
+ * double, not overlapping.  Enqueued on hip_stream.  Errors: EINVAL,
+ * EDEVICE.
+ */
+gtod_status gtod_convolve_screen(gtod_ctx* ctx, const double* in, int64_t nx,
+                                 int64_t ny, double dx_m, double dy_m,
+                                 double r_tel_m, double t_edge_db,
+                                 double* out, void* hip_stream);
+
 /* object kinds for gtod_free */
 #define GTOD_OBJ_SCREEN 0
 #define GTOD_OBJ_SPEC 1
@@ -458,7 +514,9 @@ gtod_status gtod_philox(gtod_ctx* ctx, const uint32_t* ctr, uint32_t* out,
  * FLOP (6 K F per row: three products); for the 1/f passes, complex
  * points; for the common-mode and gridding kernels of gtod_reduce, bytes
  * (4 per TOD sample read, 4 per T* sample written, 8 per channel and sample
- * of the common-mode term, 16 per spaxel, channel and cell of statistics). */
+ * of the common-mode term, 16 per spaxel, channel and cell of statistics);
+ * for the far-field table, quadrature terms (one J0 each); for the source
+ * and screen convolutions, FLOP (2 per tap and output). */
 #define GTOD_KERNEL_PANEL 0
 #define GTOD_KERNEL_GEMM_F32 1
 #define GTOD_KERNEL_GEMM_BF16 2
@@ -466,7 +524,10 @@ gtod_status gtod_philox(gtod_ctx* ctx, const uint32_t* ctr, uint32_t* out,
 #define GTOD_KERNEL_PINK2 4
 #define GTOD_KERNEL_COMMON 5
 #define GTOD_KERNEL_GRID 6
-#define GTOD_N_KERNELS 7
+#define GTOD_KERNEL_BEAM 7
+#define GTOD_KERNEL_SRC_CONV 8
+#define GTOD_KERNEL_SCREEN_CONV 9
+#define GTOD_N_KERNELS 10
 gtod_status gtod_profile_enable(gtod_ctx* ctx, int32_t enable);
 gtod_status gtod_profile_read(gtod_ctx* ctx, double* out, int32_t n_kernels);
 

@@ -41,7 +41,8 @@ def _hankel(rho, lam, R_tel, t_edge_db):
     # split at the zeros of J0 so that each piece is smooth and one-signed
     n_osc = int(k * R_tel / np.pi) + 1
     edges = np.linspace(0.0, R_tel, n_osc + 1)
-    return sum(integrate.quad(f, a, b, epsabs=0.0, epsrel=1e-13, limit=200)[0]
+    tol = 1e-15 * R_tel * R_tel
+    return sum(integrate.quad(f, a, b, epsabs=tol, epsrel=1e-12, limit=200)[0]
                for a, b in zip(edges[:-1], edges[1:]))
 
 
@@ -73,11 +74,26 @@ def convolve_source(I, nu_hz, az0, daz, el0, del_, R_tel, t_edge_db):
     rho = np.sqrt(da[None, :, None, :] ** 2 + de[:, None, :, None] ** 2)
     out = np.empty_like(I)
     src = I * np.cos(el)[:, None, None]              # I(phi', theta') cos theta'
+    rho_u, inv = np.unique(rho, return_inverse=True)
     for f in range(F):
-        Fb = far_field(rho, nu_hz[f], R_tel, t_edge_db)   # [j][i][j'][i']
+        Fb = far_field(rho_u, nu_hz[f], R_tel, t_edge_db)[inv].reshape(rho.shape)
         out[:, :, f] = a_p * daz * del_ * np.einsum("jikl,kl->ji", Fb,
                                                     src[:, :, f])
     return out
+
+
+def source_power_at(I_f, nu_f, daz, el0, del_, R_tel, t_edge_db, i, j):
+    """One node (i, j) of Eq. convolve_src at one frequency, from the
+    intensity plane I_f [n_el][n_az] of that frequency."""
+    I_f = np.asarray(I_f, dtype=np.float64)
+    n_el, n_az = I_f.shape
+    ia = np.arange(n_az)
+    ie = np.arange(n_el)
+    rho = np.sqrt(((i - ia)[None, :] * daz) ** 2 + ((j - ie)[:, None] * del_) ** 2)
+    rho_u, inv = np.unique(rho, return_inverse=True)
+    Fb = far_field(rho_u, nu_f, R_tel, t_edge_db)[inv].reshape(rho.shape)
+    src = I_f * np.cos(el0 + del_ * ie)[:, None]
+    return np.pi * R_tel ** 2 * daz * del_ * float(np.sum(Fb * src))
 
 
 def footprint_weights(dx_m, dy_m, R_tel, t_edge_db):

@@ -2,7 +2,8 @@
 spectrometers (arXiv 2604.23305, section 2): HIP kernels behind the gtod
 C-ABI (include/gtod.h), with a thin ctypes binding."""
 from .binding import (GtodError, Outputs, ScenarioRun, abi_sizes,  # noqa
-                      counters, free, load_filters, load_screen, memory,
+                      convolve_screen, convolve_source, counters, far_field,
+                      free, load_filters, load_screen, memory,
                       philox, profile_enable, profile_read, sim_init,
                       reduce, simulate_to_disk, simulate_tod, skydip,
                       spec_nep2_ref)

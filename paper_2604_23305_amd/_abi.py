@@ -119,9 +119,10 @@ SYMBOLS = ["gtod_sim_init", "gtod_load_screen", "gtod_load_filters",
            "gtod_memory", "gtod_get_counters", "gtod_spec_nep2_ref",
            "gtod_philox", "gtod_abi_sizes", "gtod_profile_enable",
            "gtod_profile_read", "gtod_skydip", "gtod_reduce",
-           "gtod_simulate_to_disk"]
+           "gtod_simulate_to_disk", "gtod_far_field", "gtod_convolve_source",
+           "gtod_convolve_screen"]
 KERNEL_NAMES = ["panel", "gemm_f32", "gemm_bf16", "pink_pass1", "pink_pass2",
-                "common", "grid"]
+                "common", "grid", "beam", "src_conv", "screen_conv"]
 MAP_MAX_N = 48
 
 _lib = None
@@ -159,6 +160,14 @@ def load():
     lib.gtod_skydip.argtypes = [vp, C.c_int32, C.c_double, C.c_double,
                                 C.c_double, C.c_int32, vp, vp, vp, vp]
     lib.gtod_reduce.argtypes = [vp, C.POINTER(ReduceDesc), vp]
+    d_ = C.c_double
+    lib.gtod_far_field.argtypes = [vp, vp, C.c_int32, C.c_int32, C.c_int32,
+                                   d_, d_, d_, d_, vp, vp]
+    lib.gtod_convolve_source.argtypes = [vp, vp, C.c_int32, C.c_int32,
+                                         C.c_int64, vp, C.c_int32, d_, d_, d_,
+                                         d_, d_, vp, C.c_int64, vp]
+    lib.gtod_convolve_screen.argtypes = [vp, vp, C.c_int64, C.c_int64, d_, d_,
+                                         d_, d_, vp, vp]
     lib.gtod_simulate_to_disk.argtypes = [vp, C.POINTER(Job), C.POINTER(Job),
                                           C.POINTER(SinkDesc),
                                           C.POINTER(C.c_double)]

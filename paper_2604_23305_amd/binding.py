@@ -220,6 +220,57 @@ def simulate_to_disk(ctx, signal: _abi.Job, pink: Optional[_abi.Job], out_dir,
     return st[0], int(st[1]), int(st[2]), int(st[3])
 
 
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+def far_field(ctx, nu_hz, n_a, n_b, da_rad, db_rad, r_tel_m, t_edge_db,
+              stream=None):
+    """Peak-normalised far field [F][n_b][n_a] (device float32) at
+    rho = sqrt((a da)^2 + (b db)^2)."""
+    import torch
+    lib = _abi.load()
+    nu = _f64(nu_hz)
+    out = torch.empty((nu.size, n_b, n_a), dtype=torch.float32, device="cuda")
+    _check(ctx, lib.gtod_far_field(ctx, _ptr(nu), nu.size, n_a, n_b, da_rad,
+                                   db_rad, r_tel_m, t_edge_db,
+                                   out.data_ptr(), _stream(stream)))
+    return out
+
+
+def convolve_source(ctx, intensity, nu_hz, daz_rad, el0_rad, del_rad,
+                    r_tel_m, t_edge_db, stream=None):
+    """Source power cube [n_el][n_az][F] (device float32, W/Hz) from a
+    specific-intensity cube of the same shape (Eq. convolve_src)."""
+    import torch
+    lib = _abi.load()
+    nu = _f64(nu_hz)
+    n_el, n_az, ld = intensity.shape
+    out = torch.empty((n_el, n_az, nu.size), dtype=torch.float32,
+                      device=intensity.device)
+    _check(ctx, lib.gtod_convolve_source(
+        ctx, intensity.data_ptr(), n_az, n_el, ld, _ptr(nu), nu.size,
+        daz_rad, el0_rad, del_rad, r_tel_m, t_edge_db, out.data_ptr(),
+        nu.size, _stream(stream)))
+    return out
+
+
+def convolve_screen(ctx, screen, dx_m, dy_m, r_tel_m, t_edge_db,
+                    stream=None):
+    """Footprint-smoothed PWV screen (device float64 [ny][nx])."""
+    import torch
+    lib = _abi.load()
+    ny, nx = screen.shape
+    out = torch.empty_like(screen)
+    _check(ctx, lib.gtod_convolve_screen(ctx, screen.data_ptr(), nx, ny, dx_m,
+                                         dy_m, r_tel_m, t_edge_db,
+                                         out.data_ptr(), _stream(stream)))
+    return out
+
+
 def philox(ctx, ctr_dev, out_dev, n, seed, stream=None):
     lib = _abi.load()
     if stream is None:

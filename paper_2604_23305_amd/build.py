@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libgtod.so")
 
 SOURCES = ["runtime.hip", "k_setup.hip", "k_panel.hip", "k_gemm_f32.hip",
            "k_gemm_bf16.hip", "k_pink.hip", "k_skydip.hip",
-           "k_reduce.hip", "sink.hip"]
+           "k_reduce.hip", "k_inputs.hip", "sink.hip"]
 
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
             "-ffp-contract=fast", "-Wall", "-Wno-unused-function",

@@ -191,6 +191,41 @@ struct ReduceArgs {
   double* weight;             // [K][C]
 };
 
+// Input preparation (section 2.2).
+struct BeamArgs {
+  int n_nodes;               // Gauss-Legendre nodes on [0, R_tel]
+  double* gl_x;              // [n_nodes] scratch: nodes on [0, 1]
+  double* gl_w;              // [n_nodes] weights on [0, 1]
+  double r_tel, t_edge_db;
+  const double* nu;          // [F] device
+  int F, n_a, n_b;
+  double da, db;             // grid spacings (rad) along a and b
+  float* table;              // [F][n_b][n_a] peak-normalised far field
+};
+struct SrcConvArgs {
+  const float* in;           // [n_el][n_az][ld_in] specific intensity
+  int64_t ld_in, ld_out;
+  int n_az, n_el, f0, nf;    // frequencies [f0, f0 + nf) of this batch
+  double el0, del, scale;    // scale = A_p daz del
+  const float* table;        // [nf][n_el][n_az] far field of the batch
+  float* out;                // [n_el][n_az][ld_out]
+};
+struct ScreenConvArgs {
+  const double* in;          // [ny][nx]
+  double* out;
+  int64_t nx, ny;
+  int rx, ry;                // footprint half widths in cells
+  double dx, dy, r_tel, t_edge_db;
+  double* w;                 // [2ry+1][2rx+1] scratch: normalised weights
+};
+constexpr int kScreenTileX = 64, kScreenTileY = 32, kMaxFootprint = 32;
+constexpr int kMaxSrcNodes = 20000;   // n_az n_el of a source grid
+void launch_gauss_legendre(double* x, double* w, int n, hipStream_t s);
+void launch_beam_table(const BeamArgs& a, hipStream_t s);
+int launch_source_conv(const SrcConvArgs& a, hipStream_t s);   // 0 ok
+void launch_screen_weights(const ScreenConvArgs& a, hipStream_t s);
+int launch_screen_conv(const ScreenConvArgs& a, hipStream_t s); // 0 ok
+
 // Context services for library parts outside the runtime file: device
 // memory charged to the context's budget, the error message, and a few
 // properties.  (The context type is defined by the runtime.)

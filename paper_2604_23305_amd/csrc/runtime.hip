@@ -1126,6 +1126,204 @@ gtod_status gtod_reduce(gtod_ctx* c, const gtod_reduce_desc* d, void* hip_stream
   return GTOD_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Quadrature nodes for the far field of a grid whose largest argument of
+// J0 is kr = 2 pi rho_max R / lambda_min.
+int beam_nodes(double kr) { return (int)round_up((int64_t)std::ceil(0.6 * kr) + 64, 32); }
+
+// Stages nu (host [F]) through the stream's pinned ring; returns the device
+// copy, valid for work enqueued on s before the slot's next reuse.
+gtod_status stage_doubles(gtod_ctx* c, StreamWs* w, hipStream_t s, const double* h,
+                          int64_t n, const double** dev, int* slot_out) {
+  if ((size_t)n * 8 > kSlotBytes) return fail(c, GTOD_EINVAL, "too many frequencies");
+  const int slot = w->slot;
+  w->slot = (w->slot + 1) % kSlots;
+  if (w->ev_used[slot]) HIP_TRY(c, hipEventSynchronize(w->ev[slot]));
+  char* hs = w->h_stage + (size_t)slot * kSlotBytes;
+  char* ds = w->d_stage + (size_t)slot * kSlotBytes;
+  std::memcpy(hs, h, (size_t)n * 8);
+  HIP_TRY(c, hipMemcpyAsync(ds, hs, (size_t)n * 8, hipMemcpyHostToDevice, s));
+  *dev = (const double*)ds;
+  *slot_out = slot;
+  return GTOD_OK;
+}
+
+gtod_status check_nu(gtod_ctx* c, const double* nu, int32_t F, double* nu_max) {
+  if (!nu || F < 1) return fail(c, GTOD_EINVAL, "need F >= 1 frequencies");
+  *nu_max = 0.0;
+  for (int f = 0; f < F; ++f) {
+    if (!finite_pos(nu[f])) return fail(c, GTOD_EINVAL, "frequencies must be positive");
+    *nu_max = std::max(*nu_max, nu[f]);
+  }
+  return GTOD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gtod_status gtod_far_field(gtod_ctx* c, const double* nu_hz, int32_t F, int32_t n_a,
+                           int32_t n_b, double da, double db, double r_tel,
+                           double t_edge_db, float* out, void* hip_stream) {
+  if (!c) return GTOD_EINVAL;
+  double nu_max;
+  gtod_status st = check_nu(c, nu_hz, F, &nu_max);
+  if (st != GTOD_OK) return st;
+  if (n_a < 1 || n_b < 1 || !(da >= 0.0) || !(db >= 0.0) || !std::isfinite(da) ||
+      !std::isfinite(db) || !finite_pos(r_tel) || !std::isfinite(t_edge_db) || !out)
+    return fail(c, GTOD_EINVAL, "bad far-field grid or aperture");
+  const double rho = std::hypot((n_a - 1) * da, (n_b - 1) * db);
+  const double kr = 2.0 * M_PI * rho * r_tel * nu_max / 299792458.0;
+  if (kr > 6000.0) return fail(c, GTOD_EINVAL, "far-field grid too oscillatory for the quadrature");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  StreamWs* w = nullptr;
+  if ((st = get_ws(c, s, &w)) != GTOD_OK) return st;
+  const double* d_nu;
+  int slot;
+  if ((st = stage_doubles(c, w, s, nu_hz, F, &d_nu, &slot)) != GTOD_OK) return st;
+  BeamArgs b{};
+  b.n_nodes = beam_nodes(kr);
+  b.gl_x = (double*)w->panel;
+  b.gl_w = b.gl_x + b.n_nodes;
+  b.r_tel = r_tel;
+  b.t_edge_db = t_edge_db;
+  b.nu = d_nu;
+  b.F = F;
+  b.n_a = n_a;
+  b.n_b = n_b;
+  b.da = da;
+  b.db = db;
+  b.table = out;
+  launch_gauss_legendre(b.gl_x, b.gl_w, b.n_nodes, s);
+  timed(c, GTOD_KERNEL_BEAM, (double)n_a * n_b * F * b.n_nodes, s,
+        [&] { launch_beam_table(b, s); });
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipEventRecord(w->ev[slot], s));
+  w->ev_used[slot] = true;
+  return GTOD_OK;
+}
+
+gtod_status gtod_convolve_source(gtod_ctx* c, const float* in, int32_t n_az, int32_t n_el,
+                                 int64_t ld_in, const double* nu_hz, int32_t F,
+                                 double daz, double el0, double del, double r_tel,
+                                 double t_edge_db, float* out, int64_t ld_out,
+                                 void* hip_stream) {
+  if (!c) return GTOD_EINVAL;
+  double nu_max;
+  gtod_status st = check_nu(c, nu_hz, F, &nu_max);
+  if (st != GTOD_OK) return st;
+  if (!in || !out || n_az < 1 || n_el < 1 || (int64_t)n_az * n_el > kMaxSrcNodes ||
+      ld_in < F || ld_out < F)
+    return fail(c, GTOD_EINVAL, "bad source grid (n_az n_el <= 20000, ld >= F)");
+  if (!finite_pos(daz) || !finite_pos(del) || !std::isfinite(el0) || !finite_pos(r_tel) ||
+      !std::isfinite(t_edge_db))
+    return fail(c, GTOD_EINVAL, "bad grid spacing, elevation or aperture");
+  const int64_t nn = (int64_t)n_az * n_el;
+  const char* ib = (const char*)in;
+  const char* ob = (const char*)out;
+  if (ib < ob + nn * ld_out * 4 && ob < ib + nn * ld_in * 4)
+    return fail(c, GTOD_EINVAL, "in and out overlap");
+  const double rho = std::hypot((n_az - 1) * daz, (n_el - 1) * del);
+  const double kr = 2.0 * M_PI * rho * r_tel * nu_max / 299792458.0;
+  if (kr > 6000.0) return fail(c, GTOD_EINVAL, "source grid too oscillatory for the quadrature");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  StreamWs* w = nullptr;
+  if ((st = get_ws(c, s, &w)) != GTOD_OK) return st;
+  const double* d_nu;
+  int slot;
+  if ((st = stage_doubles(c, w, s, nu_hz, F, &d_nu, &slot)) != GTOD_OK) return st;
+  BeamArgs b{};
+  b.n_nodes = beam_nodes(kr);
+  b.gl_x = (double*)w->panel;
+  b.gl_w = b.gl_x + b.n_nodes;
+  const int64_t head = round_up((int64_t)b.n_nodes * 16, 256);
+  const int64_t nf_max = ((int64_t)w->panel_bytes - head) / (nn * 4);
+  if (nf_max < 1) return fail(c, GTOD_EINVAL, "workspace too small for one far-field table");
+  b.r_tel = r_tel;
+  b.t_edge_db = t_edge_db;
+  b.n_a = n_az;
+  b.n_b = n_el;
+  b.da = daz;
+  b.db = del;
+  b.table = (float*)((char*)w->panel + head);
+  SrcConvArgs v{};
+  v.in = in;
+  v.ld_in = ld_in;
+  v.ld_out = ld_out;
+  v.n_az = n_az;
+  v.n_el = n_el;
+  v.el0 = el0;
+  v.del = del;
+  v.scale = M_PI * r_tel * r_tel * daz * del;
+  v.table = b.table;
+  v.out = out;
+  launch_gauss_legendre(b.gl_x, b.gl_w, b.n_nodes, s);
+  for (int f0 = 0; f0 < F; f0 += (int)nf_max) {
+    const int nf = (int)std::min<int64_t>(nf_max, F - f0);
+    b.nu = d_nu + f0;
+    b.F = nf;
+    timed(c, GTOD_KERNEL_BEAM, (double)nn * nf * b.n_nodes, s, [&] { launch_beam_table(b, s); });
+    v.f0 = f0;
+    v.nf = nf;
+    int bad = 0;
+    timed(c, GTOD_KERNEL_SRC_CONV, 2.0 * (double)nn * nn * nf, s,
+          [&] { bad = launch_source_conv(v, s); });
+    if (bad) return fail(c, GTOD_EDEVICE, "source convolution needs more LDS than the device allows");
+  }
+  HIP_TRY(c, hipGetLastError());
+  HIP_TRY(c, hipEventRecord(w->ev[slot], s));
+  w->ev_used[slot] = true;
+  return GTOD_OK;
+}
+
+gtod_status gtod_convolve_screen(gtod_ctx* c, const double* in, int64_t nx, int64_t ny,
+                                 double dx, double dy, double r_tel, double t_edge_db,
+                                 double* out, void* hip_stream) {
+  if (!c) return GTOD_EINVAL;
+  if (!in || !out || nx < 1 || ny < 1) return fail(c, GTOD_EINVAL, "bad screen");
+  if (!finite_pos(dx) || !finite_pos(dy) || !finite_pos(r_tel) || !std::isfinite(t_edge_db))
+    return fail(c, GTOD_EINVAL, "bad cell size or aperture");
+  const double fx = std::floor(r_tel / dx), fy = std::floor(r_tel / dy);
+  if (fx > kMaxFootprint || fy > kMaxFootprint)
+    return fail(c, GTOD_EINVAL, "footprint wider than 32 cells each side");
+  const char* ib = (const char*)in;
+  const char* ob = (const char*)out;
+  if (ib < ob + nx * ny * 8 && ob < ib + nx * ny * 8) return fail(c, GTOD_EINVAL, "in and out overlap");
+  HIP_TRY(c, hipSetDevice(c->device));
+  hipStream_t s = (hipStream_t)hip_stream;
+  StreamWs* w = nullptr;
+  gtod_status st;
+  if ((st = get_ws(c, s, &w)) != GTOD_OK) return st;
+  ScreenConvArgs a{};
+  a.in = in;
+  a.out = out;
+  a.nx = nx;
+  a.ny = ny;
+  a.rx = (int)fx;
+  a.ry = (int)fy;
+  a.dx = dx;
+  a.dy = dy;
+  a.r_tel = r_tel;
+  a.t_edge_db = t_edge_db;
+  a.w = (double*)w->panel;
+  launch_screen_weights(a, s);
+  int taps = 0;
+  for (int yy = -a.ry; yy <= a.ry; ++yy)
+    for (int xx = -a.rx; xx <= a.rx; ++xx)
+      taps += std::hypot(xx * dx, yy * dy) < r_tel;
+  int bad = 0;
+  timed(c, GTOD_KERNEL_SCREEN_CONV, 2.0 * taps * (double)nx * ny, s,
+        [&] { bad = launch_screen_conv(a, s); });
+  if (bad) return fail(c, GTOD_EDEVICE, "screen convolution needs more LDS than the device allows");
+  HIP_TRY(c, hipGetLastError());
+  return GTOD_OK;
+}
+
 gtod_status gtod_free(gtod_ctx* c, int32_t kind, int32_t id) {
   if (!c) return GTOD_EINVAL;
   (void)hipSetDevice(c->device);

@@ -3,8 +3,8 @@
 This module only draws and lays out inputs: frequency grids with their
 quadrature weights, PWV screens, zenith-transmission tables standing in for
 the ATM tables, filter parameters, cascade stage parameters, pre-convolved
-source cubes, spaxel offsets, user-defined scan trajectories and request
-streams.  It holds none of the simulator's arithmetic (no cascade, no filter
+source cubes and specific-intensity cubes, spaxel offsets, user-defined scan
+trajectories and request streams.  It holds none of the simulator's arithmetic (no cascade, no filter
 response, no contraction, no noise model); both the FP64 oracle and the GPU
 path consume exactly the arrays produced here.
 
@@ -196,6 +196,25 @@ def source_cube(nu_hz, n_grid: int, half_extent_rad: float, phi0: float,
     grid = dict(n_az=n_grid, n_el=n_grid, az0=phi0 - half_extent_rad,
                 daz=d, el0=theta0 - half_extent_rad, del_=d)
     return np.ascontiguousarray(cube.astype(np.float32)), grid
+
+
+def intensity_cube(nu_hz, n_grid: int, half_extent_rad: float, seed: int,
+                   n_blobs: int = 4, peak=1e-18):
+    """Specific-intensity cube float32 [n_grid][n_grid][F] (W m^-2 Hz^-1
+    sr^-1): seeded Gaussian blobs (widths 5-40 arcsec) with power-law
+    spectra, plus a faint flat floor."""
+    rng = np.random.default_rng(seed)
+    nu = np.asarray(nu_hz, dtype=np.float64)
+    off = np.linspace(-half_extent_rad, half_extent_rad, n_grid)
+    cube = np.full((n_grid, n_grid, nu.size), 1e-3 * peak)
+    for _ in range(n_blobs):
+        ca, ce = rng.uniform(-0.6, 0.6, 2) * half_extent_rad
+        s = rng.uniform(5, 40) * ARCSEC
+        shape = np.exp(-((off[None, :] - ca) ** 2 + (off[:, None] - ce) ** 2)
+                       / (2 * s * s))
+        spec = rng.uniform(0.2, 1.0) * peak * (nu / 300e9) ** rng.uniform(-1, 3)
+        cube += shape[:, :, None] * spec[None, None, :]
+    return np.ascontiguousarray(cube.astype(np.float32))
 
 
 # --------------------------------------------------------------------------
