@@ -68,6 +68,10 @@ def parse():
                          "run (gtod_simulate_to_disk) of the workload cut "
                          "to --disk-seconds, written to DIR (removed after)")
     ap.add_argument("--disk-seconds", type=float, default=360.0)
+    ap.add_argument("--prep", action="store_true",
+                    help="time the input preparation instead: source-beam "
+                         "convolution of the 121x121x3000 intensity cube and "
+                         "footprint smoothing of the 1024x262144 screen")
     ap.add_argument("--reduce", action="store_true",
                     help="after the simulation steps, time gtod_reduce "
                          "(common-mode subtraction + 31x31 inverse-variance "
@@ -168,6 +172,64 @@ def run_to_disk(args, g, torch):
     finally:
         shutil.rmtree(out_dir, ignore_errors=True)
         g.free(ctx)
+    print(json.dumps(res), flush=True)
+
+
+FP64_PEAK = 78.6e12
+
+
+def run_prep(args, g, torch, steps=3):
+    """Input preparation at the sizes of the IFU workload: source-beam
+    convolution (Eq. convolve_src) of a 121 x 121 x 3000 specific-intensity
+    cube over +-150 arcsec, and footprint smoothing (5 m aperture, -10 dB
+    taper) of the 1024 x 262144 PWV screen."""
+    import numpy as np
+    from workloads import configs, gen
+    sc = configs.c3()
+    nu = sc.spectral.nu_hz
+    n, half = 121, 150 * ARCSEC
+    d = 2 * half / (n - 1)
+    I = torch.from_numpy(gen.intensity_cube(nu, n, half, seed=8)).cuda()
+    scr = torch.from_numpy(sc.screen.pwv_mm).cuda()
+    ctx = g.sim_init(device=0, workspace_bytes=int(args.workspace_gib * (1 << 30)))
+    stream = torch.cuda.current_stream()
+    el0 = configs.THETA0 - half
+    calls = {
+        "src_conv": lambda: g.convolve_source(ctx, I, nu, d, el0, d, 5.0, -10.0),
+        "screen_conv": lambda: g.convolve_screen(ctx, scr, 0.2, 0.2, 5.0, -10.0),
+    }
+    res = {"metric": "input preparation (section 2.2)", "config": {
+        "source": f"{n}x{n}x{nu.size} intensity cube, +-150 arcsec",
+        "screen": "x".join(map(str, sc.screen.pwv_mm.shape)) + " FP64, 0.2 m cells",
+        "aperture": "R_tel 5 m, edge taper -10 dB"}}
+    for name, fn in calls.items():
+        fn()
+        torch.cuda.synchronize()
+        g.profile_enable(ctx, True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        for _ in range(steps):
+            out = fn()
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        prof = g.profile_read(ctx)
+        g.profile_enable(ctx, False)
+        del out
+        ms = ev[0].elapsed_time(ev[1]) / steps
+        kern = {}
+        for k, (kms, nl, units) in prof.items():
+            if nl:
+                kern[k] = {"launches": nl, "avg_ms": kms / nl, "total_ms": kms,
+                           "work_per_s": units / (kms / 1e3)}
+        main = kern[name]
+        res[name] = {"ms_per_call": ms, "kernels": kern,
+                     "roofline": {"kernel": name, "bound": "alu",
+                                  "achieved": main["work_per_s"] / 1e12,
+                                  "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                                  "frac": main["work_per_s"] / FP64_PEAK,
+                                  "traffic": None}}
+        print(f"# {name}: {ms:.2f} ms", file=sys.stderr, flush=True)
+    g.free(ctx)
     print(json.dumps(res), flush=True)
 
 
@@ -362,6 +424,9 @@ def main():
         return
     if args.to_disk:
         run_to_disk(args, g, torch)
+        return
+    if args.prep:
+        run_prep(args, g, torch)
         return
     if args.calib_copy:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

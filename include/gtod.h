@@ -231,7 +231,7 @@ gtod_status gtod_load_filters(gtod_ctx* ctx, const gtod_spectral_desc* desc,
  *   white noise of sample (t, k, p) uses counter (t, k, p, 0), bin j of
  *   the 1/f spectrum of series (p, k) uses counter (j, k, p, 1).
  *   PINK: PSD A_k f^-alpha_k with A_k = NEP^2_ref,k * pink_knee_hz^alpha_k
- *   (pink_alpha host [K]).
+ *   (pink_alpha host [K]); t_total <= 2^25 for PINK jobs.
  * Outputs (device, caller-owned; layout [n_pix][K][out_ld], time fastest,
  *   holding samples [out_t0, out_t0 + out_ld); out_ld = 0 means out_t0 = 0
  *   and out_ld = t_total):

@@ -95,8 +95,11 @@ struct PinkArgs {
   float* tod;
   int64_t t_total, out_ld;
   int accumulate;
-  int B2;
+  int lgB2;              // log2 of the columns per pass-2 workgroup
+  float2* tw1;           // [M2 - 1] per-stage twiddles, length M2
+  float2* tw2;           // [M1 - 1] per-stage twiddles, length M1
 };
+constexpr int kPinkTableFloat2 = 2 * 4096;   // both tables at the workspace head
 
 // setup kernels (FP64)
 struct SpecSetupArgs {
@@ -253,6 +256,7 @@ void launch_scale_spectra(float* E, float* D, float* W, float* Pref, int Fp,
 void launch_panel(const PanelArgs& a, hipStream_t s);
 void launch_gemm_f32(const GemmArgs& a, hipStream_t s);
 void launch_gemm_bf16(const GemmArgs& a, hipStream_t s);
+void launch_pink_tables(const PinkArgs& a, hipStream_t s);
 void launch_pink_pass1(const PinkArgs& a, hipStream_t s);
 void launch_pink_pass2(const PinkArgs& a, hipStream_t s);
 void launch_philox(const uint32_t* ctr, uint32_t* out, int64_t n,

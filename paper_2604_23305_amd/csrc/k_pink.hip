@@ -19,9 +19,15 @@
 //     k1, read and written as runs of B2 consecutive m2.
 // With M1 = 1 pass 1 writes the output directly.  Each DFT runs in LDS as
 // radix-2 decimation in frequency (pass 1, natural input) or in time (pass
-// 2, bit-reversed input), twiddles from a table of e^{2 pi i m / L}
-// evaluated with sincospi on exact arguments.
+// 2, bit-reversed input).  Twiddles come from per-stage tables in global
+// memory (stage with half-length h reads entries h - 1 .. 2h - 2, holding
+// e^{2 pi i pos / 2h}), so that the lanes of a stage read consecutive
+// entries; the tables are evaluated with sincospi on exact arguments once
+// per batch.  All index arithmetic is shifts and masks (lengths are powers
+// of two).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "gtod_internal.h"
 #include "philox.h"
@@ -48,22 +54,24 @@ __device__ __forceinline__ uint32_t bitrev(uint32_t v, int bits) {
   return bits == 0 ? 0u : (__brev(v) >> (32 - bits));
 }
 
-// In-place inverse DFTs of `batch` contiguous transforms of length 2^lg
-// held in bit-reversed order in buf; tw holds e^{2 pi i m / L}, m < L/2.
-__device__ void lds_dit(float2* buf, const float2* tw, int lg, int batch) {
-  const int L = 1 << lg;
-  const int half_total = (L >> 1) * batch;
+// In-place inverse DFTs of 2^lgb contiguous transforms of length 2^lg
+// held in bit-reversed order in buf; tws is the per-stage twiddle table.
+__device__ void lds_dit(float2* buf, const float2* __restrict__ tws, int lg,
+                        int lgb) {
+  if (lg == 0) return;
+  const int hl = lg - 1;                  // log2 of the butterflies per transform
+  const int half_total = 1 << (hl + lgb);
   for (int s = 1; s <= lg; ++s) {
     const int half = 1 << (s - 1);
-    const int tstride = L >> s;     // table step for this stage
+    const float2* tw = tws + (half - 1);
     for (int bf = threadIdx.x; bf < half_total; bf += blockDim.x) {
-      const int tr = bf / (L >> 1);
-      const int b = bf % (L >> 1);
-      const int pos = b % half;
-      const int i = tr * L + (b / half) * 2 * half + pos;
+      const int tr = bf >> hl;
+      const int b = bf & ((1 << hl) - 1);
+      const int pos = b & (half - 1);
+      const int i = (tr << lg) + ((b >> (s - 1)) << s) + pos;
       const int jx = i + half;
       const float2 u = buf[i];
-      const float2 v = cmul(buf[jx], tw[pos * tstride]);
+      const float2 v = cmul(buf[jx], tw[pos]);
       buf[i] = make_float2(u.x + v.x, u.y + v.y);
       buf[jx] = make_float2(u.x - v.x, u.y - v.y);
     }
@@ -85,24 +93,22 @@ __device__ __forceinline__ void store_out(const PinkArgs& a, int64_t series,
 
 }  // namespace
 
-// In-place inverse DFTs of `batch` contiguous transforms of length 2^lg,
-// natural-order input, bit-reversed output (decimation in frequency).
-__device__ void lds_dif(float2* buf, const float2* tw, int lg, int batch) {
-  const int L = 1 << lg;
-  const int half_total = (L >> 1) * batch;
+// In-place inverse DFT of one transform of length 2^lg, natural-order
+// input, bit-reversed output (decimation in frequency).
+__device__ void lds_dif(float2* buf, const float2* __restrict__ tws, int lg) {
+  if (lg == 0) return;
+  const int half_total = 1 << (lg - 1);
   for (int s = lg; s >= 1; --s) {
     const int half = 1 << (s - 1);
-    const int tstride = L >> s;
+    const float2* tw = tws + (half - 1);
     for (int bf = threadIdx.x; bf < half_total; bf += blockDim.x) {
-      const int tr = bf / (L >> 1);
-      const int b = bf % (L >> 1);
-      const int pos = b % half;
-      const int i = tr * L + (b / half) * 2 * half + pos;
+      const int pos = bf & (half - 1);
+      const int i = ((bf >> (s - 1)) << s) + pos;
       const int jx = i + half;
       const float2 u = buf[i];
       const float2 v = buf[jx];
       buf[i] = make_float2(u.x + v.x, u.y + v.y);
-      buf[jx] = cmul(make_float2(u.x - v.x, u.y - v.y), tw[pos * tstride]);
+      buf[jx] = cmul(make_float2(u.x - v.x, u.y - v.y), tw[pos]);
     }
     __syncthreads();
   }
@@ -112,9 +118,23 @@ __device__ void lds_dif(float2* buf, const float2* tw, int lg, int batch) {
 // column M1/2, or the pair (k1, M1 - k1).  Each spectral bin X_j is drawn
 // once; every Z_k is built from X_k and X_{M-k} held in LDS, two at a time
 // (e^{2 pi i (M-k)/N} = -conj e^{2 pi i k/N}).
+// Per-stage twiddle tables for transforms of length 2^lg: entry m lies in
+// the stage of half-length h = 2^floor(log2(m + 1)) and holds
+// e^{2 pi i (m - h + 1) / 2h}.
+__global__ void k_pink_tables(float2* tw1, int lg1, float2* tw2, int lg2) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  const int n1 = (1 << lg1) - 1, n2 = (1 << lg2) - 1;
+  if (m < n1 || m < n2) {
+    const int lh = 31 - __clz(m + 1);      // log2 h
+    const uint32_t pos = (uint32_t)(m + 1 - (1 << lh));
+    const float2 v = twiddle(pos, lh + 1);
+    if (m < n1) tw1[m] = v;
+    if (m < n2) tw2[m] = v;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
   __shared__ float2 buf[2][kLdsC];
-  __shared__ float2 tw[kLdsC / 2];
   const int grp = blockIdx.x;
   const int sl = blockIdx.y;
   const int64_t series = a.s0 + sl;
@@ -132,10 +152,9 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
   else { kind = 2; col[0] = grp - 1; col[1] = M1 - (grp - 1); ncol = 2; }
   col[1] = (ncol == 2) ? col[1] : col[0];
 
-  for (int m = threadIdx.x; m < M2 / 2; m += blockDim.x) tw[m] = twiddle(m, a.lgM2);
   // draw X for every bin of the group's columns (natural order)
-  for (int idx = threadIdx.x; idx < ncol * M2; idx += blockDim.x) {
-    const int c = idx / M2, k2 = idx % M2;
+  for (int idx = threadIdx.x; idx < (ncol << a.lgM2); idx += blockDim.x) {
+    const int c = idx >> a.lgM2, k2 = idx & (M2 - 1);
     const int64_t j = col[c] + (int64_t)M1 * k2;
     float2 x = make_float2(0.f, 0.f);
     if (j > 0 && j < a.M) {
@@ -185,8 +204,8 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
     }
   }
   __syncthreads();
-  lds_dif(&buf[0][0], tw, a.lgM2, 1);
-  if (ncol == 2) lds_dif(&buf[1][0], tw, a.lgM2, 1);
+  lds_dif(&buf[0][0], a.tw1, a.lgM2);
+  if (ncol == 2) lds_dif(&buf[1][0], a.tw1, a.lgM2);
   const int lgM = a.lgM1 + a.lgM2;
   for (int c = 0; c < ncol; ++c) {
     const int k1 = col[c];
@@ -205,24 +224,29 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
 
 __global__ __launch_bounds__(256) void k_pink_pass2(PinkArgs a) {
   __shared__ float2 buf[kLdsC];
-  __shared__ float2 tw[kLdsC / 2];
   const int nb = blockIdx.x;
   const int sl = blockIdx.y;
   const int64_t series = a.s0 + sl;
-  const int M1 = a.M1, M2 = a.M2, B2 = a.B2;
-  const int m20 = nb * B2;
-  for (int m = threadIdx.x; m < M1 / 2; m += blockDim.x) tw[m] = twiddle(m, a.lgM1);
-  const float2* src = a.scratch + (int64_t)sl * M1 * M2;
-  for (int idx = threadIdx.x; idx < M1 * B2; idx += blockDim.x) {
-    const int k1 = idx / B2, bb = idx % B2;
-    buf[bb * M1 + bitrev(k1, a.lgM1)] = src[(int64_t)k1 * M2 + m20 + bb];
+  const int M2 = a.M2, lgB2 = a.lgB2, B2 = 1 << lgB2;
+  const int m20 = nb << lgB2;
+  const float2* src = a.scratch + ((int64_t)sl << (a.lgM1 + a.lgM2));
+  const int n = 1 << (a.lgM1 + lgB2);
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const int k1 = idx >> lgB2, bb = idx & (B2 - 1);
+    buf[(bb << a.lgM1) + bitrev(k1, a.lgM1)] = src[(int64_t)k1 * M2 + m20 + bb];
   }
   __syncthreads();
-  lds_dit(buf, tw, a.lgM1, B2);
-  for (int idx = threadIdx.x; idx < M1 * B2; idx += blockDim.x) {
-    const int m1 = idx / B2, bb = idx % B2;
-    store_out(a, series, (int64_t)m1 * M2 + m20 + bb, buf[bb * M1 + m1]);
+  lds_dit(buf, a.tw2, a.lgM1, lgB2);
+  for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
+    const int m1 = idx >> lgB2, bb = idx & (B2 - 1);
+    store_out(a, series, (int64_t)m1 * M2 + m20 + bb, buf[(bb << a.lgM1) + m1]);
   }
+}
+
+void launch_pink_tables(const PinkArgs& a, hipStream_t s) {
+  const int n = 1 << std::max(a.lgM1, a.lgM2);
+  hipLaunchKernelGGL(k_pink_tables, dim3((n + 255) / 256), dim3(256), 0, s, a.tw1,
+                     a.lgM2, a.tw2, a.lgM1);
 }
 
 void launch_pink_pass1(const PinkArgs& a, hipStream_t s) {
@@ -231,7 +255,7 @@ void launch_pink_pass1(const PinkArgs& a, hipStream_t s) {
 }
 
 void launch_pink_pass2(const PinkArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_pink_pass2, dim3(a.M2 / a.B2, a.n_series), dim3(256), 0,
+  hipLaunchKernelGGL(k_pink_pass2, dim3(a.M2 >> a.lgB2, a.n_series), dim3(256), 0,
                      s, a);
 }
 

@@ -165,7 +165,8 @@ gtod_status get_ws(gtod_ctx* c, hipStream_t s, StreamWs** out) {
   StreamWs w;
   w.stream = s;
   w.panel_bytes = round_up((int64_t)(c->ws_bytes * 3 / 4), 256);
-  w.pink_bytes = round_up((int64_t)(c->ws_bytes - w.panel_bytes), 256);
+  w.pink_bytes = std::max<int64_t>(round_up((int64_t)(c->ws_bytes - w.panel_bytes), 256),
+                                  2 * kPinkTableFloat2 * (int64_t)sizeof(float2));
   gtod_status st;
   if ((st = dev_alloc(c, (void**)&w.panel, w.panel_bytes)) != GTOD_OK ||
       (st = dev_alloc(c, (void**)&w.pink, w.pink_bytes)) != GTOD_OK ||
@@ -278,6 +279,9 @@ gtod_status validate(gtod_ctx* c, const gtod_job& j, int idx, JobPlan* pl) {
   pl->precision = prec;
   if (j.kind == GTOD_JOB_PINK) {
     if (!j.pink_alpha) return fail(c, GTOD_EINVAL, at + "pink_alpha is NULL");
+    // the two-pass transform holds up to 4096 x 4096 complex points
+    if (j.t_total > ((int64_t)1 << 25))
+      return fail(c, GTOD_EINVAL, at + "PINK series longer than 2^25 samples");
     if (!finite_pos(j.pink_knee_hz)) return fail(c, GTOD_EINVAL, at + "pink_knee_hz must be > 0");
     if ((int64_t)j.n_pix * pl->spec->K > ((int64_t)1 << 31))
       return fail(c, GTOD_EINVAL, at + "too many series");
@@ -773,7 +777,7 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
       a.M1 = 1 << a.lgM1;
       a.M2 = 1 << a.lgM2;
       a.N = (int)N;
-      a.B2 = std::min(16, 4096 / a.M1);
+      a.lgB2 = std::min(4, 12 - a.lgM1);
       a.fs = c->fs;
       a.K = f.K;
       a.scale = (const float*)(ds + plan[i].off_scale);
@@ -785,11 +789,15 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
       a.t_total = j.t_total;
       a.out_ld = j.out_ld ? j.out_ld : j.t_total;
       a.accumulate = acc;
-      a.scratch = w->pink;
+      a.tw1 = w->pink;
+      a.tw2 = w->pink + 4096;
+      a.scratch = w->pink + kPinkTableFloat2;
+      const size_t scratch_bytes = w->pink_bytes - kPinkTableFloat2 * sizeof(float2);
       const int64_t S = (int64_t)j.n_pix * f.K;
-      int64_t per = a.M1 > 1 ? (int64_t)(w->pink_bytes / ((size_t)a.M * sizeof(float2))) : S;
+      int64_t per = a.M1 > 1 ? (int64_t)(scratch_bytes / ((size_t)a.M * sizeof(float2))) : S;
       per = std::min<int64_t>(std::min<int64_t>(per, S), 65535);
       if (per < 1) return fail(c, GTOD_EINVAL, "1/f series longer than the workspace");
+      launch_pink_tables(a, s);
       for (int64_t s0 = 0; s0 < S; s0 += per) {
         a.s0 = s0;
         a.n_series = (int)std::min<int64_t>(per, S - s0);
