@@ -123,5 +123,5 @@ def test_input_prep_errors(ctx):
     with pytest.raises(GtodError, match="EINVAL"):
         g.convolve_source(ctx, I, np.array([1e11, -1.0, 2e11]), 1e-5, 0.8, 1e-5,
                           5.0, -10.0)
-    with pytest.raises(GtodError, match="EINVAL"):
-        g.far_field(ctx, np.array([3e11]), 4, 4, 1e-2, 1e-2, 5.0, -10.0)
+    with pytest.raises(GtodError, match="EINVAL"):   # 2 pi rho R / lambda ~ 1.3e4
+        g.far_field(ctx, np.array([3e11]), 4, 4, 0.1, 0.1, 5.0, -10.0)
