@@ -30,13 +30,13 @@ namespace gtod {
 namespace {
 
 constexpr int MT = 128;   // rows per tile
-constexpr int NT = 128;   // channels per tile
+constexpr int NT = 64;    // channels per tile
 constexpr int KC = 16;    // frequency bins per LDS chunk
 constexpr int LP = KC + 4;  // padded LDS row (floats)
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
+__global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
   const int b = blockIdx.x;
   const int xcd = b & 7;
   const int l = b >> 3;
@@ -46,8 +46,9 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
   const int64_t row0 = (int64_t)tt * MT;
   const int ch0 = cg * NT;
 
-  __shared__ float smem[MT * LP + 3 * NT * LP];
-  static_assert(MT * LP + 3 * NT * LP >= 4 * kEpiWaveFloats, "epilogue LDS");
+  constexpr int kStage = MT * LP + 3 * NT * LP;
+  constexpr int kSmem = kStage > 4 * kEpiWaveFloats ? kStage : 4 * kEpiWaveFloats;
+  __shared__ float smem[kSmem];
   float* sD = smem;
   float* sB = smem + MT * LP;
 
@@ -57,22 +58,22 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
 
   // wave w multiplies time tile w (32 rows) by every live channel tile of
   // the group, so all waves of a group do the same work
-  f32x16 acc[3][4][1];
+  f32x16 acc[3][2][1];
 #pragma unroll
   for (int m = 0; m < 3; ++m)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[m][i][0][e] = 0.f;
 
   // global -> register staging: panel chunk 128 rows x 16 bins = 512 float4
-  // (2 per thread); response chunk 3 x 128 x 16 = 1536 float4 (6 per thread)
+  // (2 per thread); response chunk 3 x 64 x 16 = 768 float4 (3 per thread)
   const int64_t Fp = a.Fp;
   const int64_t KF = (int64_t)a.Kp * Fp;
   // two staging register sets: chunk c lives in set (c & 1) from its load,
   // issued two chunks ahead, until it is stored into LDS
-  float4 rdA0, rdA1, rbA0, rbA1, rbA2, rbA3, rbA4, rbA5;
-  float4 rdB0, rdB1, rbB0, rbB1, rbB2, rbB3, rbB4, rbB5;
+  float4 rdA0, rdA1, rbA0, rbA1, rbA2;
+  float4 rdB0, rdB1, rbB0, rbB1, rbB2;
 #define GTOD_LD_D(q, dst, k0n)                                               \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
@@ -82,7 +83,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
 #define GTOD_LD_B(q, dst, k0n)                                               \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
-    const int m = idx >> 9, rem = idx & 511;                                 \
+    const int m = idx >> 8, rem = idx & 255;                                 \
     const int gch = ch0 + (rem >> 2);                                        \
     dst = gch < a.Kp ? *reinterpret_cast<const float4*>(                     \
                            a.B + m * KF + (int64_t)gch * Fp + (k0n) + 4 * (rem & 3)) \
@@ -96,23 +97,21 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs a) {
 #define GTOD_ST_B(q, src)                                                    \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
-    const int m = idx >> 9, rem = idx & 511;                                 \
+    const int m = idx >> 8, rem = idx & 255;                                 \
     *reinterpret_cast<float4*>(&sB[(m * NT + (rem >> 2)) * LP + 4 * (rem & 3)]) = src; \
   }
 #define GTOD_LOAD_CHUNK(S, k0n)                                              \
   GTOD_LD_D(0, rd##S##0, k0n) GTOD_LD_D(1, rd##S##1, k0n)                    \
   GTOD_LD_B(0, rb##S##0, k0n) GTOD_LD_B(1, rb##S##1, k0n)                    \
-  GTOD_LD_B(2, rb##S##2, k0n) GTOD_LD_B(3, rb##S##3, k0n)                    \
-  GTOD_LD_B(4, rb##S##4, k0n) GTOD_LD_B(5, rb##S##5, k0n)
+  GTOD_LD_B(2, rb##S##2, k0n)
 #define GTOD_STORE_CHUNK(S)                                                  \
   GTOD_ST_D(0, rd##S##0) GTOD_ST_D(1, rd##S##1) GTOD_ST_B(0, rb##S##0)       \
-  GTOD_ST_B(1, rb##S##1) GTOD_ST_B(2, rb##S##2) GTOD_ST_B(3, rb##S##3)       \
-  GTOD_ST_B(4, rb##S##4) GTOD_ST_B(5, rb##S##5)
+  GTOD_ST_B(1, rb##S##1) GTOD_ST_B(2, rb##S##2)
 
   // channel tiles of the group that hold at least one real channel
-  bool live[4];
+  bool live[2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) live[i] = (ch0 + i * 32) < a.K;
+  for (int i = 0; i < 2; ++i) live[i] = (ch0 + i * 32) < a.K;
 
 // one chunk: two half-steps of 4 bins; lane takes bins 8*h + 4*hs + (0..3)
 #define GTOD_COMPUTE_CHUNK \
@@ -123,7 +122,7 @@ _Pragma("unroll") \
 _Pragma("unroll") \
       for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = dv[s4] * dv[s4]; \
 _Pragma("unroll") \
-      for (int i = 0; i < 4; ++i) { \
+      for (int i = 0; i < 2; ++i) { \
         if (live[i]) { \
           float4 bv[3]; \
 _Pragma("unroll") \
@@ -158,7 +157,7 @@ _Pragma("unroll") \
     }
   }
 
-  contraction_epilogue<4, 1>(a, acc, smem, row0 + wave * 32, ch0, live);
+  contraction_epilogue<2, 1>(a, acc, smem, row0 + wave * 32, ch0, live);
 }
 #undef GTOD_LD_D
 #undef GTOD_LD_B
@@ -172,7 +171,9 @@ _Pragma("unroll") \
 #undef GTOD_STORE_CHUNK
 #undef GTOD_COMPUTE_CHUNK
 
-void launch_gemm_f32(const GemmArgs& a, hipStream_t s) {
+void launch_gemm_f32(const GemmArgs& a0, hipStream_t s) {
+  GemmArgs a = a0;
+  a.n_cg = (a.Kp + NT - 1) / NT;
   const int64_t n_tt8 = round_up(a.n_tt, 8);
   const int64_t blocks = n_tt8 * a.n_cg;
   hipLaunchKernelGGL(k_gemm_f32, dim3((unsigned)blocks), dim3(256), 0, s, a);
