@@ -13,10 +13,12 @@
 // weight m / s^2, and the cells of all spaxels are combined with it.
 //
 // Kernels: setup (scan table, mean PWV, channel transmission), common (one
-// thread per (t, k): M and optionally T*), grid (one block per (spaxel,
-// channel): cell sums in LDS), combine (one thread per (channel, cell)).
-// The common and grid kernels each stream the TOD once: HBM-bound, with
-// the FP64 transcendental work per sample (one sine, exp, expm1) alongside.
+// thread per sample and 16 channels: M and optionally T*), grid (one block
+// per (spaxel, channel): cell sums in LDS), combine (one thread per
+// (channel, cell)).  The common and grid kernels each stream the TOD once;
+// per sample they evaluate one FP64 expm1 (eta = 1 + expm1(ln eta), so
+// 1 - eta keeps its relative precision), with the cosecant shared by the
+// channels of a thread in the common kernel.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -99,27 +101,48 @@ __global__ __launch_bounds__(kRdThreads) void k_rd_channel(ReduceArgs a) {
   if (threadIdx.x == 0) a.lnz[k] = (D > 0.0) ? log(N / D) : NAN;
 }
 
+// One thread per sample t and kRdChan channels of the group: the cosecant
+// of each spaxel is evaluated once per (spaxel, sample) and used for every
+// channel; eta and 1 - eta both come from one expm1.
+constexpr int kRdChan = 16;
 __global__ __launch_bounds__(kRdThreads) void k_rd_common(ReduceArgs a) {
   const int64_t t = (int64_t)blockIdx.x * kRdThreads + threadIdx.x;
-  const int kl = blockIdx.y;
+  const int kl0 = blockIdx.y * kRdChan;
   if (t >= a.T) return;
-  const int k = a.k0 + kl;
-  const double lz = a.lnz[k];
+  const int nk = min(kRdChan, a.kg - kl0);
+  double lz[kRdChan], sum[kRdChan];
+#pragma unroll
+  for (int q = 0; q < kRdChan; ++q) {
+    lz[q] = q < nk ? a.lnz[a.k0 + kl0 + q] : 0.0;
+    sum[q] = 0.0;
+  }
   const double th = a.scan_tab[t].y + a.theta0;
-  double sum = 0.0;
+  const int64_t rowK = a.ld;                      // stride between channels
   for (int p = 0; p < a.P; ++p) {
     if (!a.off[p]) continue;
-    const double l = lz / sin(th + a.dtheta[p]);
-    sum += (double)a.tod[((int64_t)p * a.K + k) * a.ld + t] / -expm1(l);
+    const double csc = 1.0 / sin(th + a.dtheta[p]);
+    const float* src = a.tod + ((int64_t)p * a.K + a.k0 + kl0) * a.ld + t;
+#pragma unroll
+    for (int q = 0; q < kRdChan; ++q)
+      if (q < nk) sum[q] += (double)src[q * rowK] / -expm1(lz[q] * csc);
   }
-  const double M = sum / (double)a.n_out;
-  if (a.M) a.M[(int64_t)kl * a.T + t] = M;
+#pragma unroll
+  for (int q = 0; q < kRdChan; ++q) {
+    sum[q] /= (double)a.n_out;
+    if (q < nk && a.M) a.M[(int64_t)(kl0 + q) * a.T + t] = sum[q];
+  }
   if (!a.t_star) return;
   for (int p = 0; p < a.P; ++p) {
-    const double l = lz / sin(th + a.dtheta[p]);
-    const double eta = exp(l);
-    const int64_t o = ((int64_t)p * a.K + k) * a.ld + t;
-    a.t_star[o] = (float)(((double)a.tod[o] + expm1(l) * M) / eta);
+    const double csc = 1.0 / sin(th + a.dtheta[p]);
+    const int64_t o = ((int64_t)p * a.K + a.k0 + kl0) * a.ld + t;
+#pragma unroll
+    for (int q = 0; q < kRdChan; ++q) {
+      if (q < nk) {
+        const double em = expm1(lz[q] * csc);     // eta - 1
+        a.t_star[o + q * rowK] =
+            (float)(((double)a.tod[o + q * rowK] + em * sum[q]) / (1.0 + em));
+      }
+    }
   }
 }
 
@@ -146,8 +169,8 @@ __global__ __launch_bounds__(kRdThreads) void k_rd_grid(ReduceArgs a) {
   const float* row = a.tod + ((int64_t)p * a.K + k) * a.ld;
   const double* Mr = a.M + (int64_t)kl * a.T;
   auto tstar = [&](int64_t t, double th) {
-    const double l = lz / sin(th + dth);
-    return ((double)row[t] + expm1(l) * Mr[t]) / exp(l);
+    const double em = expm1(lz / sin(th + dth));  // eta - 1
+    return ((double)row[t] + em * Mr[t]) / (1.0 + em);
   };
   const double shift = tstar(0, a.scan_tab[0].y);
   __syncthreads();
@@ -203,7 +226,8 @@ void launch_reduce_setup(const ReduceArgs& a, hipStream_t s) {
 
 void launch_reduce_common(const ReduceArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(k_rd_common,
-                     dim3((unsigned)((a.T + kRdThreads - 1) / kRdThreads), a.kg),
+                     dim3((unsigned)((a.T + kRdThreads - 1) / kRdThreads),
+                          (a.kg + kRdChan - 1) / kRdChan),
                      dim3(kRdThreads), 0, s, a);
 }
 
