@@ -247,7 +247,7 @@ hipStream_t ctx_sink_stream(gtod_ctx* c, int which);
 
 void launch_reduce_setup(const ReduceArgs& a, hipStream_t s);
 void launch_reduce_common(const ReduceArgs& a, hipStream_t s);
-void launch_reduce_grid(const ReduceArgs& a, hipStream_t s);
+int launch_reduce_grid(const ReduceArgs& a, hipStream_t s);  // 0 ok
 void launch_reduce_combine(const ReduceArgs& a, hipStream_t s);
 void launch_spec_setup(const SpecSetupArgs& a, const PassTable& pt,
                        hipStream_t s);

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kRdThreads) void k_rd_common(ReduceArgs a) {
     sum[q] /= (double)a.n_out;
     if (q < nk && a.M) a.M[(int64_t)(kl0 + q) * a.T + t] = sum[q];
   }
-  if (!a.t_star) return;
+  if (!a.t_star || a.map_n > 0) return;
   for (int p = 0; p < a.P; ++p) {
     const double csc = 1.0 / sin(th + a.dtheta[p]);
     const int64_t o = ((int64_t)p * a.K + a.k0 + kl0) * a.ld + t;
@@ -146,56 +146,85 @@ __global__ __launch_bounds__(kRdThreads) void k_rd_common(ReduceArgs a) {
   }
 }
 
-// One block per (spaxel, channel of the group), spaxel fastest so that the
-// blocks sharing a channel's M row run together.  Cell sums of v = T* -
-// shift (shift = the block's first sample) in LDS; the variance is
-// (S2 - S1^2 / m) / (m - 1).
+// One block per (spaxel, kRdGridChan channels of the group), spaxel
+// fastest so that the blocks sharing those channels' M rows run together.
+// The sample's cosecant and cell are evaluated once for all its channels;
+// cell count (common to the channels), and per channel the sums of v =
+// T* - shift (shift = the channel's first sample) and v^2, accumulate in
+// LDS; the variance is (S2 - S1^2 / m) / (m - 1).  When T* is requested
+// with maps, this kernel also stores it (for every sample, in or out of
+// the map).
+constexpr int kRdGridChan = 4;
 __global__ __launch_bounds__(kRdThreads) void k_rd_grid(ReduceArgs a) {
-  __shared__ unsigned cnt[kMaxMapN * kMaxMapN];
-  __shared__ double s1[kMaxMapN * kMaxMapN];
-  __shared__ double s2[kMaxMapN * kMaxMapN];
-  const int p = blockIdx.x % a.P;
-  const int kl = blockIdx.x / a.P;
-  const int k = a.k0 + kl;
+  extern __shared__ double gsm[];
   const int C = a.map_n * a.map_n;
+  double* s1 = gsm;                                   // [G][C]
+  double* s2 = gsm + kRdGridChan * C;                 // [G][C]
+  unsigned* cnt = (unsigned*)(gsm + 2 * kRdGridChan * C);   // [C]
+  const int p = blockIdx.x % a.P;
+  const int kl0 = (blockIdx.x / a.P) * kRdGridChan;
+  const int nk = min(kRdGridChan, a.kg - kl0);
   for (int c = threadIdx.x; c < C; c += kRdThreads) {
     cnt[c] = 0u;
-    s1[c] = 0.0;
-    s2[c] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kRdGridChan; ++q) {
+      s1[q * C + c] = 0.0;
+      s2[q * C + c] = 0.0;
+    }
   }
-  const double lz = a.lnz[k];
   const double dth = a.theta0 + a.dtheta[p];
   const double dph = a.dphi[p];
-  const float* row = a.tod + ((int64_t)p * a.K + k) * a.ld;
-  const double* Mr = a.M + (int64_t)kl * a.T;
-  auto tstar = [&](int64_t t, double th) {
-    const double em = expm1(lz / sin(th + dth));  // eta - 1
-    return ((double)row[t] + em * Mr[t]) / (1.0 + em);
-  };
-  const double shift = tstar(0, a.scan_tab[0].y);
+  double lz[kRdGridChan], shift[kRdGridChan];
+  const float* row[kRdGridChan];
+  const double* Mr[kRdGridChan];
+  const double csc0 = 1.0 / sin(a.scan_tab[0].y + dth);
+#pragma unroll
+  for (int q = 0; q < kRdGridChan; ++q) {
+    const int kq = min(kl0 + q, a.kg - 1);     // dead slots repeat the last channel
+    lz[q] = a.lnz[a.k0 + kq];
+    row[q] = a.tod + ((int64_t)p * a.K + a.k0 + kq) * a.ld;
+    Mr[q] = a.M + (int64_t)kq * a.T;
+    const double em = expm1(lz[q] * csc0);
+    shift[q] = ((double)row[q][0] + em * Mr[q][0]) / (1.0 + em);
+  }
+  float* out_ts = a.t_star ? a.t_star + ((int64_t)p * a.K + a.k0 + kl0) * a.ld : nullptr;
   __syncthreads();
   for (int64_t t = threadIdx.x; t < a.T; t += kRdThreads) {
     const double2 sc = a.scan_tab[t];
     const int c = map_cell(a, sc.x + dph, sc.y + a.dtheta[p]);
-    if (c < 0) continue;
-    const double v = tstar(t, sc.y) - shift;
-    atomicAdd(&cnt[c], 1u);
-    atomicAdd(&s1[c], v);
-    atomicAdd(&s2[c], v * v);
-  }
-  __syncthreads();
-  double2* out = a.stats + ((int64_t)p * a.kg + kl) * C;
-  for (int c = threadIdx.x; c < C; c += kRdThreads) {
-    const double m = (double)cnt[c];
-    double w = 0.0, mean = 0.0;
-    if (m >= 2.0) {
-      const double var = (s2[c] - s1[c] * s1[c] / m) / (m - 1.0);
-      if (var > 0.0) {
-        w = m / var;
-        mean = s1[c] / m + shift;
+    if (c < 0 && !out_ts) continue;
+    const double csc = 1.0 / sin(sc.y + dth);
+    if (c >= 0) atomicAdd(&cnt[c], 1u);
+#pragma unroll
+    for (int q = 0; q < kRdGridChan; ++q) {
+      if (q < nk) {
+        const double em = expm1(lz[q] * csc);     // eta - 1
+        const double ts = ((double)row[q][t] + em * Mr[q][t]) / (1.0 + em);
+        if (out_ts) out_ts[q * a.ld + t] = (float)ts;
+        if (c >= 0) {
+          const double v = ts - shift[q];
+          atomicAdd(&s1[q * C + c], v);
+          atomicAdd(&s2[q * C + c], v * v);
+        }
       }
     }
-    out[c] = make_double2(w, mean);
+  }
+  __syncthreads();
+  for (int q = 0; q < nk; ++q) {
+    double2* out = a.stats + ((int64_t)p * a.kg + kl0 + q) * C;
+    for (int c = threadIdx.x; c < C; c += kRdThreads) {
+      const double m = (double)cnt[c];
+      double w = 0.0, mean = 0.0;
+      if (m >= 2.0) {
+        const double S1 = s1[q * C + c], S2 = s2[q * C + c];
+        const double var = (S2 - S1 * S1 / m) / (m - 1.0);
+        if (var > 0.0) {
+          w = m / var;
+          mean = S1 / m + shift[q];
+        }
+      }
+      out[c] = make_double2(w, mean);
+    }
   }
 }
 
@@ -231,8 +260,15 @@ void launch_reduce_common(const ReduceArgs& a, hipStream_t s) {
                      dim3(kRdThreads), 0, s, a);
 }
 
-void launch_reduce_grid(const ReduceArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_rd_grid, dim3((unsigned)(a.P * a.kg)), dim3(kRdThreads), 0, s, a);
+int launch_reduce_grid(const ReduceArgs& a, hipStream_t s) {
+  const int C = a.map_n * a.map_n;
+  const size_t lds = (size_t)C * (2 * kRdGridChan * sizeof(double) + sizeof(unsigned));
+  if (hipFuncSetAttribute((const void*)k_rd_grid,
+                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+    return 1;
+  const int groups = (a.kg + kRdGridChan - 1) / kRdGridChan;
+  hipLaunchKernelGGL(k_rd_grid, dim3((unsigned)(a.P * groups)), dim3(kRdThreads), lds, s, a);
+  return 0;
 }
 
 void launch_reduce_combine(const ReduceArgs& a, hipStream_t s) {

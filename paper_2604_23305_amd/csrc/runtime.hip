@@ -1120,11 +1120,16 @@ gtod_status gtod_reduce(gtod_ctx* c, const gtod_reduce_desc* d, void* hip_stream
     a.k0 = (int)k0;
     a.kg = (int)std::min<int64_t>(kg, K - k0);
     const double samples = (double)P * a.kg * T;
-    const double cm_bytes = samples * (d->t_star ? 8.0 : 4.0) + (maps ? 8.0 * a.kg * T : 0.0);
+    // with maps the gridding kernel writes T*; the common-mode kernel only M
+    const double cm_bytes = samples * ((d->t_star && !maps) ? 8.0 : 4.0) +
+                            (maps ? 8.0 * a.kg * T : 0.0);
     timed(c, GTOD_KERNEL_COMMON, cm_bytes, s, [&] { launch_reduce_common(a, s); });
     if (maps) {
-      const double gb = samples * 4.0 + 8.0 * a.kg * T + 16.0 * P * a.kg * C;
-      timed(c, GTOD_KERNEL_GRID, gb, s, [&] { launch_reduce_grid(a, s); });
+      const double gb = samples * (d->t_star ? 8.0 : 4.0) + 8.0 * a.kg * T +
+                        16.0 * P * a.kg * C;
+      int bad = 0;
+      timed(c, GTOD_KERNEL_GRID, gb, s, [&] { bad = launch_reduce_grid(a, s); });
+      if (bad) return fail(c, GTOD_EDEVICE, "gridding needs more LDS than the device allows");
       launch_reduce_combine(a, s);
     }
   }
