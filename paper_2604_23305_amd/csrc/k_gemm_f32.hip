@@ -1,7 +1,7 @@
 // Filterbank contraction on the FP32 matrix cores, with the photon-noise
 // epilogue (sections 2.5-2.7).
 //
-// For a tile of 128 rows (consecutive samples of one pixel) x 128 channels
+// For a tile of 128 rows (consecutive samples of one pixel) x 64 channels
 // the kernel accumulates, over the frequency axis,
 //   C0 = dP B0,   C1 = dP B1',   C2 = dP^2 B2
 // with v_mfma_f32_32x32x2_f32.  The MFMA "A" operand is the channel-major
@@ -12,13 +12,16 @@
 // Epilogue: P_KID = c0 + C0, NEP^2 = c1 + C1 + C2, sigma = sqrt(NEP^2 f/2),
 // P_wn = sigma z with z from Philox counter (t, k, p, 0).
 //
-// Workgroup: 4 waves along time, each 32 samples x all (up to 4) live
-// 32-channel tiles of the group, so a partly filled last group costs in
-// proportion to its live tiles.  Operands are staged through LDS in depth chunks of
-// 16 frequency bins; inside a chunk lane l takes bins 8*(l/32) .. +8, read
-// as 16-byte vectors.  Tile index -> workgroup mapping keeps the channel
-// groups of one time tile on the same XCD so the panel tile is fetched once
-// into that XCD's L2.
+// Workgroup: 4 waves along time, each 32 samples x both (or the one live)
+// 32-channel tiles of the group: 96 accumulator registers and 232 VGPRs in
+// all, so two workgroups share a CU and one's barriers and epilogue overlap
+// the other's MFMAs.  Operands are staged through LDS in depth chunks of 32
+// frequency bins (row pitch 36 floats: the 16-byte reads of 8 or 16
+// consecutive lanes fall in distinct banks), loaded into registers two
+// chunks ahead; inside a chunk lane l takes bins 16*(l/32) + 4*hs .. +3 for
+// the four quarter-steps hs.  Tile index -> workgroup mapping keeps the
+// channel groups of one time tile on the same XCD so the panel tile is
+// fetched once into that XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include "gtod_internal.h"
@@ -31,7 +34,7 @@ namespace {
 
 constexpr int MT = 128;   // rows per tile
 constexpr int NT = 64;    // channels per tile
-constexpr int KC = 16;    // frequency bins per LDS chunk
+constexpr int KC = 32;    // frequency bins per LDS chunk
 constexpr int LP = KC + 4;  // padded LDS row (floats)
 
 }  // namespace
@@ -72,52 +75,56 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
   const int64_t KF = (int64_t)a.Kp * Fp;
   // two staging register sets: chunk c lives in set (c & 1) from its load,
   // issued two chunks ahead, until it is stored into LDS
-  float4 rdA0, rdA1, rbA0, rbA1, rbA2;
-  float4 rdB0, rdB1, rbB0, rbB1, rbB2;
+  float4 rdA0, rdA1, rdA2, rdA3, rbA0, rbA1, rbA2, rbA3, rbA4, rbA5;
+  float4 rdB0, rdB1, rdB2, rdB3, rbB0, rbB1, rbB2, rbB3, rbB4, rbB5;
 #define GTOD_LD_D(q, dst, k0n)                                               \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
-    dst = *reinterpret_cast<const float4*>(a.panel + (row0 + (idx >> 2)) * Fp + \
-                                           (k0n) + 4 * (idx & 3));           \
+    dst = *reinterpret_cast<const float4*>(a.panel + (row0 + (idx >> 3)) * Fp + \
+                                           (k0n) + 4 * (idx & 7));           \
   }
 #define GTOD_LD_B(q, dst, k0n)                                               \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
-    const int m = idx >> 8, rem = idx & 255;                                 \
-    const int gch = ch0 + (rem >> 2);                                        \
+    const int m = idx >> 9, rem = idx & 511;                                 \
+    const int gch = ch0 + (rem >> 3);                                        \
     dst = gch < a.Kp ? *reinterpret_cast<const float4*>(                     \
-                           a.B + m * KF + (int64_t)gch * Fp + (k0n) + 4 * (rem & 3)) \
+                           a.B + m * KF + (int64_t)gch * Fp + (k0n) + 4 * (rem & 7)) \
                      : make_float4(0.f, 0.f, 0.f, 0.f);                      \
   }
 #define GTOD_ST_D(q, src)                                                    \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
-    *reinterpret_cast<float4*>(&sD[(idx >> 2) * LP + 4 * (idx & 3)]) = src;  \
+    *reinterpret_cast<float4*>(&sD[(idx >> 3) * LP + 4 * (idx & 7)]) = src;  \
   }
 #define GTOD_ST_B(q, src)                                                    \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
-    const int m = idx >> 8, rem = idx & 255;                                 \
-    *reinterpret_cast<float4*>(&sB[(m * NT + (rem >> 2)) * LP + 4 * (rem & 3)]) = src; \
+    const int m = idx >> 9, rem = idx & 511;                                 \
+    *reinterpret_cast<float4*>(&sB[(m * NT + (rem >> 3)) * LP + 4 * (rem & 7)]) = src; \
   }
 #define GTOD_LOAD_CHUNK(S, k0n)                                              \
   GTOD_LD_D(0, rd##S##0, k0n) GTOD_LD_D(1, rd##S##1, k0n)                    \
+  GTOD_LD_D(2, rd##S##2, k0n) GTOD_LD_D(3, rd##S##3, k0n)                    \
   GTOD_LD_B(0, rb##S##0, k0n) GTOD_LD_B(1, rb##S##1, k0n)                    \
-  GTOD_LD_B(2, rb##S##2, k0n)
+  GTOD_LD_B(2, rb##S##2, k0n) GTOD_LD_B(3, rb##S##3, k0n)                    \
+  GTOD_LD_B(4, rb##S##4, k0n) GTOD_LD_B(5, rb##S##5, k0n)
 #define GTOD_STORE_CHUNK(S)                                                  \
-  GTOD_ST_D(0, rd##S##0) GTOD_ST_D(1, rd##S##1) GTOD_ST_B(0, rb##S##0)       \
-  GTOD_ST_B(1, rb##S##1) GTOD_ST_B(2, rb##S##2)
+  GTOD_ST_D(0, rd##S##0) GTOD_ST_D(1, rd##S##1) GTOD_ST_D(2, rd##S##2)       \
+  GTOD_ST_D(3, rd##S##3) GTOD_ST_B(0, rb##S##0) GTOD_ST_B(1, rb##S##1)       \
+  GTOD_ST_B(2, rb##S##2) GTOD_ST_B(3, rb##S##3) GTOD_ST_B(4, rb##S##4)       \
+  GTOD_ST_B(5, rb##S##5)
 
   // channel tiles of the group that hold at least one real channel
   bool live[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) live[i] = (ch0 + i * 32) < a.K;
 
-// one chunk: two half-steps of 4 bins; lane takes bins 8*h + 4*hs + (0..3)
+// one chunk: four quarter-steps of 4 bins; lane takes bins 16*h + 4*hs + (0..3)
 #define GTOD_COMPUTE_CHUNK \
 _Pragma("unroll") \
-    for (int hs = 0; hs < 2; ++hs) { \
-      const float4 dv = *reinterpret_cast<const float4*>(&sD[(wave * 32 + c) * LP + 8 * h + 4 * hs]); \
+    for (int hs = 0; hs < 4; ++hs) { \
+      const float4 dv = *reinterpret_cast<const float4*>(&sD[(wave * 32 + c) * LP + 16 * h + 4 * hs]); \
       float dsq[4]; \
 _Pragma("unroll") \
       for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = dv[s4] * dv[s4]; \
@@ -128,7 +135,7 @@ _Pragma("unroll") \
 _Pragma("unroll") \
           for (int m = 0; m < 3; ++m) \
             bv[m] = *reinterpret_cast<const float4*>( \
-                &sB[(m * NT + i * 32 + c) * LP + 8 * h + 4 * hs]); \
+                &sB[(m * NT + i * 32 + c) * LP + 16 * h + 4 * hs]); \
 _Pragma("unroll") \
           for (int s4 = 0; s4 < 4; ++s4) { \
             acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[0][s4], dv[s4], acc[0][i][0], 0, 0, 0); \
