@@ -13,6 +13,10 @@
 // of P, so the 16-bit operands give about 1e-7 relative error on P_KID.
 // dP is split once per workgroup, when a chunk is staged into LDS; the
 // response halves come pre-split from the spectral setup.
+// Workgroup: 128 samples x 64 channels, 4 waves along time, each 32
+// samples x both 32-channel tiles (96 accumulator registers, 194 VGPRs in
+// all), so two workgroups share a CU and hide each other's barriers and
+// epilogues.
 #include <hip/hip_runtime.h>
 
 #include "gtod_internal.h"
@@ -27,13 +31,13 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MT = 128;
-constexpr int NT = 128;
+constexpr int NT = 64;
 constexpr int KC = 32;        // bins per chunk = 2 MFMA steps of 16
 constexpr int LPB = KC + 8;   // padded LDS row in bf16 (80 bytes)
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
+__global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
   const int b = blockIdx.x;
   const int xcd = b & 7;
   const int l = b >> 3;
@@ -44,32 +48,31 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
   const int ch0 = cg * NT;
 
   // sD: [3][MT][LPB] dP hi, dP lo, (dP^2) hi; sB: [5][NT][LPB] B0h B0l B1h B1l B2h
-  __shared__ float smem[(3 * MT * LPB + 5 * NT * LPB) / 2];
-  static_assert((3 * MT * LPB + 5 * NT * LPB) / 2 >= 4 * kEpiWaveFloats, "epilogue LDS");
+  constexpr int kStage = (3 * MT * LPB + 5 * NT * LPB) / 2;
+  constexpr int kSmem = kStage > 4 * kEpiWaveFloats ? kStage : 4 * kEpiWaveFloats;
+  __shared__ float smem[kSmem];
   __bf16* sD = reinterpret_cast<__bf16*>(smem);
   __bf16* sB = sD + 3 * MT * LPB;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int wt = wave & 1, wc = wave >> 1;
+  // wave w: rows 32 w .. 32 w + 31 x both 32-channel tiles of the group
   const int h = lane >> 5, c = lane & 31;
 
-  f32x16 acc[3][2][2];
+  f32x16 acc[3][2][1];
 #pragma unroll
   for (int m = 0; m < 3; ++m)
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[m][i][j][e] = 0.f;
+      for (int e = 0; e < 16; ++e) acc[m][i][0][e] = 0.f;
 
   const int64_t Fp = a.Fp;
   const int64_t KF = (int64_t)a.Kp * Fp;
   // panel chunk: 128 rows x 32 floats = 1024 float4, 4 per thread;
-  // response chunk: 5 x 128 x 32 bf16 = 2560 x 16 bytes, 10 per thread
+  // response chunk: 5 x 64 x 32 bf16 = 1280 x 16 bytes, 5 per thread
   float4 rd0, rd1, rd2, rd3;
-  uint4 rb0, rb1, rb2, rb3, rb4, rb5, rb6, rb7, rb8, rb9;
+  uint4 rb0, rb1, rb2, rb3, rb4;
 #define GTOD_LD_D(q, dst, k0n)                                               \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
@@ -79,7 +82,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
 #define GTOD_LD_B(q, dst, k0n)                                               \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
-    const int mm = idx >> 9, rem = idx & 511;                                \
+    const int mm = idx >> 8, rem = idx & 255;                                \
     const int gch = ch0 + (rem >> 2);                                        \
     /* mm: 0 B0h, 1 B0l, 2 B1h, 3 B1l, 4 B2h */                              \
     const uint16_t* base = (mm & 1) ? a.Bl : a.Bh;                           \
@@ -106,25 +109,22 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
 #define GTOD_ST_B(q, src)                                                    \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
-    const int mm = idx >> 9, rem = idx & 511;                                \
+    const int mm = idx >> 8, rem = idx & 255;                                \
     *reinterpret_cast<uint4*>(&sB[(mm * NT + (rem >> 2)) * LPB + 8 * (rem & 3)]) = src; \
   }
 #define GTOD_LOAD_CHUNK(k0n)                                                 \
   GTOD_LD_D(0, rd0, k0n) GTOD_LD_D(1, rd1, k0n) GTOD_LD_D(2, rd2, k0n)       \
   GTOD_LD_D(3, rd3, k0n)                                                     \
   GTOD_LD_B(0, rb0, k0n) GTOD_LD_B(1, rb1, k0n) GTOD_LD_B(2, rb2, k0n)       \
-  GTOD_LD_B(3, rb3, k0n) GTOD_LD_B(4, rb4, k0n) GTOD_LD_B(5, rb5, k0n)       \
-  GTOD_LD_B(6, rb6, k0n) GTOD_LD_B(7, rb7, k0n) GTOD_LD_B(8, rb8, k0n)       \
-  GTOD_LD_B(9, rb9, k0n)
+  GTOD_LD_B(3, rb3, k0n) GTOD_LD_B(4, rb4, k0n)
 #define GTOD_STORE_CHUNK                                                     \
   GTOD_ST_D(0, rd0) GTOD_ST_D(1, rd1) GTOD_ST_D(2, rd2) GTOD_ST_D(3, rd3)   \
   GTOD_ST_B(0, rb0) GTOD_ST_B(1, rb1)                                       \
-  GTOD_ST_B(2, rb2) GTOD_ST_B(3, rb3) GTOD_ST_B(4, rb4) GTOD_ST_B(5, rb5)   \
-  GTOD_ST_B(6, rb6) GTOD_ST_B(7, rb7) GTOD_ST_B(8, rb8) GTOD_ST_B(9, rb9)
+  GTOD_ST_B(2, rb2) GTOD_ST_B(3, rb3) GTOD_ST_B(4, rb4)
 
   bool live[2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) live[i] = (ch0 + wc * 64 + i * 32) < a.K;
+  for (int i = 0; i < 2; ++i) live[i] = (ch0 + i * 32) < a.K;
 
   GTOD_LOAD_CHUNK(0)
   for (int k0 = 0; k0 < a.Fp; k0 += KC) {
@@ -135,25 +135,24 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
 #pragma unroll
     for (int s = 0; s < KC / 16; ++s) {
       const int col = 16 * s + 8 * h;
-      bf16x8 dh[2], dl[2], ds[2];
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int o = (wt * 64 + j * 32 + c) * LPB + col;
-        dh[j] = *reinterpret_cast<const bf16x8*>(&sD[o]);
-        dl[j] = *reinterpret_cast<const bf16x8*>(&sD[MT * LPB + o]);
-        ds[j] = *reinterpret_cast<const bf16x8*>(&sD[2 * MT * LPB + o]);
+      bf16x8 dh[1], dl[1], ds[1];
+      {
+        const int o = (wave * 32 + c) * LPB + col;
+        dh[0] = *reinterpret_cast<const bf16x8*>(&sD[o]);
+        dl[0] = *reinterpret_cast<const bf16x8*>(&sD[MT * LPB + o]);
+        ds[0] = *reinterpret_cast<const bf16x8*>(&sD[2 * MT * LPB + o]);
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         if (live[i]) {
-        const int ob = (wc * 64 + i * 32 + c) * LPB + col;
+        const int ob = (i * 32 + c) * LPB + col;
         const bf16x8 b0h = *reinterpret_cast<const bf16x8*>(&sB[0 * NT * LPB + ob]);
         const bf16x8 b0l = *reinterpret_cast<const bf16x8*>(&sB[1 * NT * LPB + ob]);
         const bf16x8 b1h = *reinterpret_cast<const bf16x8*>(&sB[2 * NT * LPB + ob]);
         const bf16x8 b1l = *reinterpret_cast<const bf16x8*>(&sB[3 * NT * LPB + ob]);
         const bf16x8 b2h = *reinterpret_cast<const bf16x8*>(&sB[4 * NT * LPB + ob]);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) {
+        for (int j = 0; j < 1; ++j) {
           acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0l, dh[j], acc[0][i][j], 0, 0, 0);
           acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0h, dl[j], acc[0][i][j], 0, 0, 0);
           acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0h, dh[j], acc[0][i][j], 0, 0, 0);
@@ -167,7 +166,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
     }
   }
 
-  contraction_epilogue<2, 2>(a, acc, smem, row0 + wt * 64, ch0 + wc * 64, live);
+  contraction_epilogue<2, 1>(a, acc, smem, row0 + wave * 32, ch0, live);
 }
 #undef GTOD_LD_D
 #undef GTOD_LD_B
@@ -176,7 +175,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs a) {
 #undef GTOD_LOAD_CHUNK
 #undef GTOD_STORE_CHUNK
 
-void launch_gemm_bf16(const GemmArgs& a, hipStream_t s) {
+void launch_gemm_bf16(const GemmArgs& a0, hipStream_t s) {
+  GemmArgs a = a0;
+  a.n_cg = (a.Kp + NT - 1) / NT;
   const int64_t n_tt8 = round_up(a.n_tt, 8);
   const int64_t blocks = n_tt8 * a.n_cg;
   hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)blocks), dim3(256), 0, s, a);
