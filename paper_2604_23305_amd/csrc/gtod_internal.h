@@ -78,7 +78,8 @@ struct GemmArgs {
   float* tod;
   float* p_kid;
   float* sigma;
-  int n_tt, n_cg;
+  int n_tt;              // 128-row time tiles of the chunk
+  int n_cg;              // channel groups (set by each contraction launcher)
 };
 
 struct PinkArgs {

@@ -913,7 +913,6 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
         ga.Tc = Tc;
         ga.Tpad = Tpad;
         ga.n_tt = (int)((int64_t)np * Tpad / kRowPad);
-        ga.n_cg = (f.Kp + 127) / 128;
         if (plan[i].precision == GTOD_PREC_SPLIT_BF16)
           timed(c, GTOD_KERNEL_GEMM_BF16, flop, s, [&] { launch_gemm_bf16(ga, s); });
         else
