@@ -52,7 +52,7 @@ WORKLOADS = {
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--precision", default=None, choices=["fp32", "split"])
@@ -297,6 +297,76 @@ def cpu_reduce(sc, seconds_hint=None):
             "sample": f"1 channel x {sc.n_pix} spaxels x {T} samples"}
 
 
+def copy_gbs(torch, n_bytes=1 << 30, reps=5):
+    """Device-to-device copy bandwidth (bytes read + written per second),
+    the practical ceiling for the elementwise kernels."""
+    src = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    del src, dst
+    return 2.0 * n_bytes / (ms / 1e3) / 1e9
+
+
+def d2h_gbs(torch, tod, n_bytes=1 << 30, reps=3):
+    """Device-to-host copy of part of the TOD into pinned memory (GB/s);
+    reported beside the result, never as it."""
+    flat = tod.reshape(-1)[: n_bytes // 4]
+    host = torch.empty(flat.numel(), dtype=torch.float32, pin_memory=True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    host.copy_(flat, non_blocking=True)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        host.copy_(flat, non_blocking=True)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    return flat.numel() * 4 / (ms / 1e3) / 1e9
+
+
+def elementwise(kern, workload, copy):
+    """HBM view of the elementwise kernels (panel, 1/f passes): algorithmic
+    GB/s against the 8 TB/s peak and against the measured copy bandwidth,
+    plus the measured fetch+write bytes where a profile holds them."""
+    out = {}
+    for name in ("panel", "pink_pass1", "pink_pass2"):
+        if name not in kern:
+            continue
+        gbs = kern[name]["alg_gbs"]
+        d = {"alg_gbs": gbs, "frac_hbm_peak": gbs * 1e9 / HBM_PEAK,
+             "frac_copy": gbs / copy}
+        tf = os.path.join(ROOT, "profiles", f"traffic_{name}_{workload}.json")
+        if os.path.exists(tf):
+            b = json.load(open(tf))["bytes_per_launch"]
+            meas = b / (kern[name]["avg_ms"] / 1e3) / 1e9
+            d.update({"measured_gbs": meas,
+                      "measured_frac_hbm_peak": meas * 1e9 / HBM_PEAK})
+        out[name] = d
+    return out
+
+
+def end_to_end(value, sc, prec_name):
+    """Detector-samples/s against the whole-path bound: the contraction at
+    its matrix-core peak (6 F FLOP per detector-sample; the split path runs
+    7 BF16 products for every 3) and the algorithmic HBM bytes per
+    detector-sample ((16 F + 4 K) / K: four source spectra per row and the
+    output)."""
+    F, K = sc.F, sc.K
+    flop = 6.0 * F * (7.0 / 3.0 if prec_name == "split" else 1.0)
+    compute = PEAK[prec_name] / flop
+    hbm = HBM_PEAK / ((16.0 * F + 4.0 * K) / K)
+    bound = min(compute, hbm)
+    return {"compute_bound": compute, "hbm_bound": hbm, "frac": value / bound}
+
+
 def kernel_table(prof):
     """Per-kernel figures from the library's event timing, with the
     algorithmic work the library reports per kernel (FLOP for the
@@ -434,6 +504,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    copy = copy_gbs(torch)
     prec_name = args.precision or ("split" if args.workload == "c4" else "fp32")
     prec = g.PREC_SPLIT_BF16 if prec_name == "split" else g.PREC_FP32
     t_setup = time.perf_counter()
@@ -512,8 +583,14 @@ def main():
                    "tod_unit": "K" if kel else "W",
                    "parallelism": "single GPU"},
         "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
-                       "p99": float(np.percentile(step_ms, 99))},
+                       "p99": float(np.percentile(step_ms, 99)),
+                       "min": float(np.min(step_ms)),
+                       "max": float(np.max(step_ms))},
         "roofline": roof,
+        "elementwise": elementwise(kern, args.workload, copy),
+        "end_to_end": end_to_end(value, sc, prec_name),
+        "copy_gbs": copy,
+        "d2h_gbs": d2h_gbs(torch, out.tod),
         "kernels": kern,
     }
     g.free(ctx)
