@@ -237,3 +237,47 @@ def test_strict_range_rejects_leaving_screen():
             g.simulate_tod(c, [run.signal_job(out)])
     finally:
         g.free(c)
+
+
+def test_empty_calls_and_windows_change_nothing(ctx):
+    sc = configs.c1(t_total=400)
+    run = g.ScenarioRun(ctx, sc)
+    out = run.alloc()
+    out.tod.fill_(3.0)
+    g.simulate_tod(ctx, [])
+    g.simulate_tod(ctx, [run.signal_job(out, 200, 200)])
+    torch.cuda.synchronize()
+    assert torch.all(out.tod == 3.0)
+
+
+def test_pink_length_limit_is_an_error(ctx):
+    sc = tiny_scenario(F=16, K=3, P=1, T=8)
+    sc.pink_alpha = np.ones(3)
+    run = g.ScenarioRun(ctx, sc)
+    tod = torch.zeros(4, device="cuda")
+    job = run.pink_job(tod, accumulate=False)
+    job.t_total = (1 << 25) + 1
+    with pytest.raises(g.GtodError, match="EINVAL"):
+        g.simulate_tod(ctx, [job])
+
+
+def test_pixel_subset_with_pix0_matches_full_job(ctx):
+    """A job over pixels [2, 5) with pix0 = 2 gives, bit for bit, rows 2..4
+    of one job over all seven pixels (signal, photon and 1/f noise)."""
+    sc = tiny_scenario(F=40, K=5, P=7, T=1500)
+    sc.pink_alpha = np.array([1.0, 0.7, 1.3, 2.0, 0.5])
+    run = g.ScenarioRun(ctx, sc)
+    full = run.alloc()
+    g.simulate_tod(ctx, [run.pink_job(full.tod, accumulate=False),
+                         run.signal_job(full, accumulate=True)])
+    part = torch.zeros((3, sc.K, sc.t_total), device="cuda")
+    sig = run.signal_job(full, accumulate=True)
+    sig.n_pix, sig.pix0 = 3, 2
+    sig.dphi_rad = run.dphi[2:].ctypes.data
+    sig.dtheta_rad = run.dtheta[2:].ctypes.data
+    sig.tod = part.data_ptr()
+    pk = run.pink_job(part, accumulate=False)
+    pk.n_pix, pk.pix0 = 3, 2
+    g.simulate_tod(ctx, [pk, sig])
+    torch.cuda.synchronize()
+    assert torch.equal(part, full.tod[2:5])
