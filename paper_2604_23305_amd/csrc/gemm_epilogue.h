@@ -5,7 +5,8 @@
 //
 // Each wave owns NI x NJ accumulator tiles of 32 channels x 32 samples (3
 // products); tile (i, j) starts at channel ch_base + 32 i and row
-// row_base + 32 j.  A tile is first written to the wave's slice of LDS with
+// row_base + 32 j.  A tile is first written to the wave's own LDS slice
+// (kEpiWaveFloats floats at spk, distinct for each wave) with
 // static register indices, then read back by a compact loop in which lane
 // l handles sample (l mod 32) of channel rows 2s + l/32: stores are runs of
 // 32 consecutive samples.
@@ -25,11 +26,10 @@ constexpr int kEpiWaveFloats = 2 * 32 * kEpiPitch;
 
 template <int NI, int NJ>
 __device__ __forceinline__ void contraction_epilogue(
-    const GemmArgs& a, f32x16 (&acc)[3][NI][NJ], float* smem,
+    const GemmArgs& a, f32x16 (&acc)[3][NI][NJ], float* spk,
     int64_t row_base, int ch_base, const bool (&live)[NI]) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
   const int h = lane >> 5, c = lane & 31;
-  float* spk = smem + wave * kEpiWaveFloats;
   float* sn2 = spk + 32 * kEpiPitch;
 #pragma unroll
   for (int i = 0; i < NI; ++i) {

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
     }
   }
 
-  contraction_epilogue<2, 1>(a, acc, smem, row0 + wave * 32, ch0, live);
+  contraction_epilogue<2, 1>(a, acc, smem + wave * kEpiWaveFloats, row0 + wave * 32, ch0, live);
 }
 #undef GTOD_LD_D
 #undef GTOD_LD_B

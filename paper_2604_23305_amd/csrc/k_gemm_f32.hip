@@ -13,15 +13,25 @@
 // P_wn = sigma z with z from Philox counter (t, k, p, 0).
 //
 // Workgroup: 4 waves along time, each 32 samples x both (or the one live)
-// 32-channel tiles of the group: 96 accumulator registers and 232 VGPRs in
-// all, so two workgroups share a CU and one's barriers and epilogue overlap
-// the other's MFMAs.  Operands are staged through LDS in depth chunks of 32
-// frequency bins (row pitch 36 floats: the 16-byte reads of 8 or 16
-// consecutive lanes fall in distinct banks), loaded into registers two
-// chunks ahead; inside a chunk lane l takes bins 16*(l/32) + 4*hs .. +3 for
-// the four quarter-steps hs.  Tile index -> workgroup mapping keeps the
-// channel groups of one time tile on the same XCD so the panel tile is
-// fetched once into that XCD's L2.
+// 32-channel tiles of the group: 96 accumulator registers, about 150 VGPRs
+// and 60 KB of LDS, so two workgroups share a CU and one's barriers and
+// epilogue overlap the other's MFMAs.
+//
+// Operand staging: depth chunks of 16 frequency bins go straight from
+// global memory into a three-stage LDS ring with global_load_lds_dwordx4
+// (no register staging), two chunks ahead of the MFMAs.  A stage holds the
+// panel [128][16] and the three responses [3][64][16] in unpadded 64-byte
+// rows; the 16-byte slot of bin quad q in row r is q ^ swz(r), which puts
+// the 16-byte reads of 32 consecutive rows into distinct bank groups.
+// The DMA is issued from inline assembly: the compiler does not know that
+// it writes LDS, so it does not wait for it before every LDS read of the
+// other stages.  Ordering comes from the kernel itself: before chunk c is
+// read, each wave waits until at most the 5 DMAs of chunk c + 1 are in
+// flight, and a barrier makes every wave's part of chunk c visible; the
+// stage that chunk c + 2 overwrites was last read before that barrier.
+//
+// Tile index -> workgroup mapping keeps the channel groups of one time tile
+// on the same XCD so the panel tile is fetched once into that XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include "gtod_internal.h"
@@ -34,8 +44,30 @@ namespace {
 
 constexpr int MT = 128;   // rows per tile
 constexpr int NT = 64;    // channels per tile
-constexpr int KC = 32;    // frequency bins per LDS chunk
-constexpr int LP = KC + 4;  // padded LDS row (floats)
+constexpr int KC = 16;    // frequency bins per chunk
+// One stage: panel [MT][KC] then responses [3][NT][KC], rows unpadded.
+constexpr int kStageFloats = MT * KC + 3 * NT * KC;
+
+__device__ __forceinline__ int swz(int row) { return ((row >> 1) ^ (row >> 2)) & 3; }
+
+__device__ __forceinline__ uint32_t lds_addr(float* p) {
+  return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float*)p;
+}
+
+// One wave-wide direct-to-LDS load: lane i moves the 16 bytes at g to LDS
+// byte address m0 + 16 i (m0 uniform).  M0 is a reserved register the
+// compiler does not save around inline assembly; no other code in this
+// kernel uses it.  The s_nop covers the M0 write -> LDS DMA hazard.
+__device__ __forceinline__ void dma16(const float* g, uint32_t m0) {
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Winline-asm"
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
+               :: "s"(m0), "v"(g) : "memory", "m0");
+#pragma clang diagnostic pop
+}
+
+// s_waitcnt with vmcnt = n (< 16) and the other counters left free.
+#define GTOD_WAIT_VM(n) __builtin_amdgcn_s_waitcnt(0x3f70 | (n))
 
 }  // namespace
 
@@ -49,18 +81,17 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
   const int64_t row0 = (int64_t)tt * MT;
   const int ch0 = cg * NT;
 
-  constexpr int kStage = MT * LP + 3 * NT * LP;
-  constexpr int kSmem = kStage > 4 * kEpiWaveFloats ? kStage : 4 * kEpiWaveFloats;
-  __shared__ float smem[kSmem];
-  float* sD = smem;
-  float* sB = smem + MT * LP;
+  // the ring; after the loop, stage 0 holds the epilogue slices of waves
+  // 0 and 1, stage 1 those of waves 2 and 3
+  static_assert(kStageFloats >= 2 * kEpiWaveFloats, "epilogue LDS");
+  __shared__ float st0[kStageFloats];
+  __shared__ float st1[kStageFloats];
+  __shared__ float st2[kStageFloats];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int h = lane >> 5, c = lane & 31;
 
-  // wave w multiplies time tile w (32 rows) by every live channel tile of
-  // the group, so all waves of a group do the same work
   f32x16 acc[3][2][1];
 #pragma unroll
   for (int m = 0; m < 3; ++m)
@@ -69,114 +100,96 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[m][i][0][e] = 0.f;
 
-  // global -> register staging: panel chunk 128 rows x 16 bins = 512 float4
-  // (2 per thread); response chunk 3 x 64 x 16 = 768 float4 (3 per thread)
   const int64_t Fp = a.Fp;
   const int64_t KF = (int64_t)a.Kp * Fp;
-  // two staging register sets: chunk c lives in set (c & 1) from its load,
-  // issued two chunks ahead, until it is stored into LDS
-  float4 rdA0, rdA1, rdA2, rdA3, rbA0, rbA1, rbA2, rbA3, rbA4, rbA5;
-  float4 rdB0, rdB1, rdB2, rdB3, rbB0, rbB1, rbB2, rbB3, rbB4, rbB5;
-#define GTOD_LD_D(q, dst, k0n)                                               \
-  {                                                                          \
-    const int idx = tid + (q) * 256;                                         \
-    dst = *reinterpret_cast<const float4*>(a.panel + (row0 + (idx >> 3)) * Fp + \
-                                           (k0n) + 4 * (idx & 7));           \
+  // Direct-to-LDS loads: one wave instruction moves 16 rows x 16 bins (64
+  // lanes x 16 bytes) into 1 KB of LDS, lane i to offset 16 i.  Lane i
+  // takes row i / 4 of its block and the bin quad (i % 4) ^ swz(row).
+  const int lr = lane >> 2, lq = lane & 3;
+  // panel: wave w moves rows 32 w + 16 q + lr, q = 0, 1
+  const float* gp[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int r = wave * 32 + q * 16 + lr;
+    gp[q] = a.panel + (row0 + r) * Fp + 4 * (lq ^ swz(r));
   }
-#define GTOD_LD_B(q, dst, k0n)                                               \
-  {                                                                          \
-    const int idx = tid + (q) * 256;                                         \
-    const int m = idx >> 9, rem = idx & 511;                                 \
-    const int gch = ch0 + (rem >> 3);                                        \
-    dst = gch < a.Kp ? *reinterpret_cast<const float4*>(                     \
-                           a.B + m * KF + (int64_t)gch * Fp + (k0n) + 4 * (rem & 7)) \
-                     : make_float4(0.f, 0.f, 0.f, 0.f);                      \
+  // responses: wave w moves blocks u = 3 w + q: matrix u / 4, channels
+  // 16 (u % 4) + lr (clamped into the padded matrix; dead rows are unused)
+  const float* gb[3];
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const int u = wave * 3 + q;
+    const int m = u >> 2, r = ((u & 3) << 4) + lr;
+    const int gch = min(ch0 + r, a.Kp - 1);
+    gb[q] = a.B + m * KF + (int64_t)gch * Fp + 4 * (lq ^ swz(m * NT + r));
   }
-#define GTOD_ST_D(q, src)                                                    \
-  {                                                                          \
-    const int idx = tid + (q) * 256;                                         \
-    *reinterpret_cast<float4*>(&sD[(idx >> 3) * LP + 4 * (idx & 7)]) = src;  \
+  // issue chunk `chunk` into the stage at LDS byte address ST
+#define GTOD_ISSUE(ST, chunk)                                                 \
+  {                                                                           \
+    const int k0_ = (chunk) * KC;                                             \
+    _Pragma("unroll") for (int q = 0; q < 2; ++q)                             \
+      dma16(gp[q] + k0_, (ST) + 4u * ((wave_s * 32 + q * 16) * KC));         \
+    _Pragma("unroll") for (int q = 0; q < 3; ++q) {                           \
+      const int u = wave_s * 3 + q;                                           \
+      dma16(gb[q] + k0_,                                                      \
+            (ST) + 4u * (MT * KC + ((u >> 2) * NT + ((u & 3) << 4)) * KC));  \
+    }                                                                         \
   }
-#define GTOD_ST_B(q, src)                                                    \
-  {                                                                          \
-    const int idx = tid + (q) * 256;                                         \
-    const int m = idx >> 9, rem = idx & 511;                                 \
-    *reinterpret_cast<float4*>(&sB[(m * NT + (rem >> 3)) * LP + 4 * (rem & 7)]) = src; \
-  }
-#define GTOD_LOAD_CHUNK(S, k0n)                                              \
-  GTOD_LD_D(0, rd##S##0, k0n) GTOD_LD_D(1, rd##S##1, k0n)                    \
-  GTOD_LD_D(2, rd##S##2, k0n) GTOD_LD_D(3, rd##S##3, k0n)                    \
-  GTOD_LD_B(0, rb##S##0, k0n) GTOD_LD_B(1, rb##S##1, k0n)                    \
-  GTOD_LD_B(2, rb##S##2, k0n) GTOD_LD_B(3, rb##S##3, k0n)                    \
-  GTOD_LD_B(4, rb##S##4, k0n) GTOD_LD_B(5, rb##S##5, k0n)
-#define GTOD_STORE_CHUNK(S)                                                  \
-  GTOD_ST_D(0, rd##S##0) GTOD_ST_D(1, rd##S##1) GTOD_ST_D(2, rd##S##2)       \
-  GTOD_ST_D(3, rd##S##3) GTOD_ST_B(0, rb##S##0) GTOD_ST_B(1, rb##S##1)       \
-  GTOD_ST_B(2, rb##S##2) GTOD_ST_B(3, rb##S##3) GTOD_ST_B(4, rb##S##4)       \
-  GTOD_ST_B(5, rb##S##5)
 
-  // channel tiles of the group that hold at least one real channel
   bool live[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) live[i] = (ch0 + i * 32) < a.K;
 
-// one chunk: four quarter-steps of 4 bins; lane takes bins 16*h + 4*hs + (0..3)
-#define GTOD_COMPUTE_CHUNK \
-_Pragma("unroll") \
-    for (int hs = 0; hs < 4; ++hs) { \
-      const float4 dv = *reinterpret_cast<const float4*>(&sD[(wave * 32 + c) * LP + 16 * h + 4 * hs]); \
-      float dsq[4]; \
-_Pragma("unroll") \
-      for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = dv[s4] * dv[s4]; \
-_Pragma("unroll") \
-      for (int i = 0; i < 2; ++i) { \
-        if (live[i]) { \
-          float4 bv[3]; \
-_Pragma("unroll") \
-          for (int m = 0; m < 3; ++m) \
-            bv[m] = *reinterpret_cast<const float4*>( \
-                &sB[(m * NT + i * 32 + c) * LP + 16 * h + 4 * hs]); \
-_Pragma("unroll") \
-          for (int s4 = 0; s4 < 4; ++s4) { \
+  const int n_chunks = a.Fp / KC;
+  const int rd = wave * 32 + c;
+  // wave index and stage addresses as wave-uniform (scalar) values for M0
+  const int wave_s = __builtin_amdgcn_readfirstlane(wave);
+  const uint32_t lds0 = __builtin_amdgcn_readfirstlane(lds_addr(st0));
+  const uint32_t lds1 = __builtin_amdgcn_readfirstlane(lds_addr(st1));
+  const uint32_t lds2 = __builtin_amdgcn_readfirstlane(lds_addr(st2));
+  GTOD_ISSUE(lds0, 0)
+  if (n_chunks > 1) GTOD_ISSUE(lds1, 1)
+  // one chunk: SR the stage read now, SW the stage chunk kc + 2 goes to
+#define GTOD_STEP(SR, SW, kc)                                                  \
+  {                                                                            \
+    if ((kc) + 1 < n_chunks) { GTOD_WAIT_VM(5); } else { GTOD_WAIT_VM(0); }    \
+    __builtin_amdgcn_s_barrier();                                              \
+    if ((kc) + 2 < n_chunks) GTOD_ISSUE(SW, (kc) + 2)                           \
+    const float* sD = (SR);                                                    \
+    const float* sB = (SR) + MT * KC;                                          \
+    _Pragma("unroll") for (int hs = 0; hs < 2; ++hs) {                         \
+      const int q = 2 * h + hs;                                                \
+      const float4 dv = *reinterpret_cast<const float4*>(&sD[rd * KC + 4 * (q ^ swz(rd))]); \
+      float dsq[4];                                                            \
+      _Pragma("unroll") for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = dv[s4] * dv[s4]; \
+      _Pragma("unroll") for (int i = 0; i < 2; ++i) {                          \
+        if (live[i]) {                                                         \
+          float4 bv[3];                                                        \
+          _Pragma("unroll") for (int m = 0; m < 3; ++m) {                      \
+            const int rb = m * NT + i * 32 + c;                                \
+            bv[m] = *reinterpret_cast<const float4*>(&sB[rb * KC + 4 * (q ^ swz(rb))]); \
+          }                                                                    \
+          _Pragma("unroll") for (int s4 = 0; s4 < 4; ++s4) {                   \
             acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[0][s4], dv[s4], acc[0][i][0], 0, 0, 0); \
             acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[1][s4], dv[s4], acc[1][i][0], 0, 0, 0); \
             acc[2][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[2][s4], dsq[s4], acc[2][i][0], 0, 0, 0); \
-          } \
-        } \
-      } \
-    }
-
-  const int n_chunks = a.Fp / KC;
-  GTOD_LOAD_CHUNK(A, 0)
-  if (n_chunks > 1) { GTOD_LOAD_CHUNK(B, KC) }
-  for (int kc = 0; kc < n_chunks; kc += 2) {
-    __syncthreads();
-    GTOD_STORE_CHUNK(A)
-    __syncthreads();
-    if (kc + 2 < n_chunks) { GTOD_LOAD_CHUNK(A, (kc + 2) * KC) }
-    GTOD_COMPUTE_CHUNK
-    if (kc + 1 < n_chunks) {
-      __syncthreads();
-      GTOD_STORE_CHUNK(B)
-      __syncthreads();
-      if (kc + 3 < n_chunks) { GTOD_LOAD_CHUNK(B, (kc + 3) * KC) }
-      GTOD_COMPUTE_CHUNK
-    }
+          }                                                                    \
+        }                                                                      \
+      }                                                                        \
+    }                                                                          \
   }
-
-  contraction_epilogue<2, 1>(a, acc, smem, row0 + wave * 32, ch0, live);
+  for (int kc = 0; kc < n_chunks; kc += 3) {
+    GTOD_STEP(st0, lds2, kc)
+    if (kc + 1 < n_chunks) GTOD_STEP(st1, lds0, kc + 1)
+    if (kc + 2 < n_chunks) GTOD_STEP(st2, lds1, kc + 2)
+  }
+  __syncthreads();   // every wave is done with the ring before the epilogue reuses it
+  float* const spk = (wave < 2 ? st0 : st1) + (wave & 1) * kEpiWaveFloats;
+  contraction_epilogue<2, 1>(a, acc, spk, row0 + wave * 32, ch0, live);
 }
-#undef GTOD_LD_D
-#undef GTOD_LD_B
-#undef GTOD_ST_D
-#undef GTOD_ST_B
-#undef GTOD_LD_D
-#undef GTOD_LD_B
-#undef GTOD_ST_D
-#undef GTOD_ST_B
-#undef GTOD_LOAD_CHUNK
-#undef GTOD_STORE_CHUNK
-#undef GTOD_COMPUTE_CHUNK
+#undef GTOD_WAIT_VM
+#undef GTOD_ISSUE
+#undef GTOD_STEP
 
 void launch_gemm_f32(const GemmArgs& a0, hipStream_t s) {
   GemmArgs a = a0;

@@ -70,16 +70,18 @@ def test_c1_full_parity(ctx, noise):
     np.testing.assert_allclose(out.pwv.cpu().numpy(), ref["pwv"], rtol=1e-7)
 
 
+@pytest.mark.parametrize("prec", [g.PREC_FP32, g.PREC_SPLIT_BF16])
 @pytest.mark.parametrize("filt", ["filterbank", "lorentz", "matrix"])
 @pytest.mark.parametrize("shape", [(8, 3, 2, 5), (37, 33, 3, 131),
                                    (100, 130, 2, 300)])
-def test_tiny_and_ragged_shapes(ctx, filt, shape):
-    """Shapes that leave ragged F, K and T tiles; every cascade kind."""
+def test_tiny_and_ragged_shapes(ctx, filt, shape, prec):
+    """Shapes that leave ragged F, K and T tiles; every cascade kind; both
+    contraction kernels (a K tail of one or two 32-channel tiles)."""
     F, K, P, T = shape
     sc = tiny_scenario(F=F, K=K, P=P, T=T, filt=filt,
                        stages=configs.cascade_table2())
     ref = oracle.tod.simulate(sc)
-    _, out = run_signal(ctx, sc)
+    _, out = run_signal(ctx, sc, precision=prec)
     _compare(sc, out, ref)
 
 
