@@ -97,10 +97,10 @@ struct PinkArgs {
   int64_t t_total, out_ld;
   int accumulate;
   int lgB2;              // log2 of the columns per pass-2 workgroup
-  float2* tw1;           // [M2 - 1] per-stage twiddles, length M2
-  float2* tw2;           // [M1 - 1] per-stage twiddles, length M1
+  const float2* tab;     // [4096] e^{2 pi i m / 4096}
+  float2* tab_w;         // the same table, written by k_pink_tables
 };
-constexpr int kPinkTableFloat2 = 2 * 4096;   // both tables at the workspace head
+constexpr int kPinkTableFloat2 = 2 * 4096;   // reserved at the workspace head
 
 // setup kernels (FP64)
 struct SpecSetupArgs {

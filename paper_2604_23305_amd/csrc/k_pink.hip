@@ -17,14 +17,22 @@
 //     e^{2 pi i k1 m2 / M}, stored contiguous in m2;
 //   pass 2, per (series, block of B2 consecutive m2): length-M1 DFTs over
 //     k1, read and written as runs of B2 consecutive m2.
-// With M1 = 1 pass 1 writes the output directly.  Each DFT runs in LDS as
-// radix-2 decimation in frequency (pass 1, natural input) or in time (pass
-// 2, bit-reversed input).  Twiddles come from per-stage tables in global
-// memory (stage with half-length h reads entries h - 1 .. 2h - 2, holding
-// e^{2 pi i pos / 2h}), so that the lanes of a stage read consecutive
-// entries; the tables are evaluated with sincospi on exact arguments once
-// per batch.  All index arithmetic is shifts and masks (lengths are powers
-// of two).
+// With M1 = 1 pass 1 writes the output directly.
+//
+// Each DFT runs in LDS as self-sorting (Stockham) passes of radix 16, then
+// one of radix 2, 4 or 8 for the remaining factor: a thread loads the R
+// inputs j + r L/R of one group into registers, multiplies them by
+// e^{2 pi i r (j mod S) / (S R)} (S = product of the radices before),
+// does the length-R DFT in registers and stores output s at
+// (j div S) S R + (j mod S) + s S.  Input and output are in natural order.
+// Pass twiddles come from one table of e^{2 pi i m / 4096} in global
+// memory (evaluated with sincospi on exact arguments); the in-register
+// DFTs use the constants cos, sin(2 pi m / 16).  Pass 1 keeps its one or
+// two transforms contiguous in LDS with one float2 of padding after every
+// 16, so that the stride-16 stores of the first pass hit distinct banks;
+// pass 2 interleaves its B2 transforms (element i of transform t at
+// i B2 + t, t fastest across lanes), which makes every access consecutive.
+// All index arithmetic is shifts and masks (lengths are powers of two).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,10 +44,16 @@ namespace gtod {
 
 namespace {
 
-constexpr int kLdsC = 4096;   // complex values per workgroup
+constexpr int kLdsC = 4096;   // complex values per transform set
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
   return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) {
+  return make_float2(a.x + b.x, a.y + b.y);
+}
+__device__ __forceinline__ float2 csub(float2 a, float2 b) {
+  return make_float2(a.x - b.x, a.y - b.y);
 }
 
 __device__ __forceinline__ float2 twiddle(uint32_t num, int lg_den) {
@@ -50,32 +64,128 @@ __device__ __forceinline__ float2 twiddle(uint32_t num, int lg_den) {
   return make_float2(c, s);
 }
 
-__device__ __forceinline__ uint32_t bitrev(uint32_t v, int bits) {
-  return bits == 0 ? 0u : (__brev(v) >> (32 - bits));
+// cos and sin of 2 pi m / 16, m = 0 .. 7, rounded to float
+__device__ constexpr float kCos16[8] = {
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f,
+    0.0f, -0.38268343236508977f, -0.70710678118654752f, -0.92387953251128674f};
+__device__ constexpr float kSin16[8] = {
+    0.0f, 0.38268343236508977f, 0.70710678118654752f, 0.92387953251128674f,
+    1.0f, 0.92387953251128674f, 0.70710678118654752f, 0.38268343236508977f};
+
+// a e^{2 pi i m / 16}; m is a constant once the callers are unrolled
+__device__ __forceinline__ float2 mul_w16(float2 a, int m) {
+  if (m == 0) return a;
+  if (m == 4) return make_float2(-a.y, a.x);
+  return make_float2(a.x * kCos16[m] - a.y * kSin16[m],
+                     a.x * kSin16[m] + a.y * kCos16[m]);
 }
 
-// In-place inverse DFTs of 2^lgb contiguous transforms of length 2^lg
-// held in bit-reversed order in buf; tws is the per-stage twiddle table.
-__device__ void lds_dit(float2* buf, const float2* __restrict__ tws, int lg,
-                        int lgb) {
-  if (lg == 0) return;
-  const int hl = lg - 1;                  // log2 of the butterflies per transform
-  const int half_total = 1 << (hl + lgb);
-  for (int s = 1; s <= lg; ++s) {
+constexpr int brev_c(int x, int bits) {
+  int r = 0;
+  for (int b = 0; b < bits; ++b) r |= ((x >> b) & 1) << (bits - 1 - b);
+  return r;
+}
+
+// In-register inverse DFT of length 2^LGR (<= 16), natural order in and
+// out: bit-reversed copy, then radix-2 decimation in time.
+template <int LGR>
+__device__ __forceinline__ void dft_inv(float2 (&v)[1 << LGR]) {
+  constexpr int R = 1 << LGR;
+  float2 u[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) u[brev_c(r, LGR)] = v[r];
+#pragma unroll
+  for (int s = 1; s <= LGR; ++s) {
     const int half = 1 << (s - 1);
-    const float2* tw = tws + (half - 1);
-    for (int bf = threadIdx.x; bf < half_total; bf += blockDim.x) {
-      const int tr = bf >> hl;
-      const int b = bf & ((1 << hl) - 1);
+#pragma unroll
+    for (int b = 0; b < R / 2; ++b) {
       const int pos = b & (half - 1);
-      const int i = (tr << lg) + ((b >> (s - 1)) << s) + pos;
-      const int jx = i + half;
-      const float2 u = buf[i];
-      const float2 v = cmul(buf[jx], tw[pos]);
-      buf[i] = make_float2(u.x + v.x, u.y + v.y);
-      buf[jx] = make_float2(u.x - v.x, u.y - v.y);
+      const int i = ((b >> (s - 1)) << s) + pos;
+      const float2 x = u[i];
+      const float2 y = mul_w16(u[i + half], pos << (4 - s));
+      u[i] = cadd(x, y);
+      u[i + half] = csub(x, y);
     }
-    __syncthreads();
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) v[r] = u[r];
+}
+
+// Element i of transform t: pass 1 keeps transforms contiguous with one
+// float2 of padding after every 16; pass 2 interleaves them.
+struct AddrPadded {
+  int lgL;
+  __device__ int operator()(int t, int i) const {
+    const int x = (t << lgL) + i;
+    return x + (x >> 4);
+  }
+};
+struct AddrInterleaved {
+  int lgT;
+  __device__ int operator()(int t, int i) const { return (i << lgT) + t; }
+};
+
+// One Stockham pass of radix 2^LGR over the 2^lgT transforms of length
+// 2^lgL in buf, after passes whose radices multiply to 2^lgNs.  EMAX is
+// the largest element count of any caller (groups per thread <= EMAX /
+// (256 R)).  Transform t and group j of group g: t slowest for contiguous
+// transforms (TFAST = false), fastest for interleaved ones.
+template <int LGR, int EMAX, bool TFAST, class Addr>
+__device__ __forceinline__ void stockham_pass(float2* buf, Addr addr, int lgL, int lgT,
+                                              int lgNs, const float2* __restrict__ tab) {
+  constexpr int R = 1 << LGR;
+  constexpr int GM = (EMAX / 256 / R) > 0 ? EMAX / 256 / R : 1;
+  const int lgJ = lgL - LGR;                     // log2 of the groups per transform
+  const int nG = 1 << (lgT + lgJ);
+  float2 v[GM][R];
+#pragma unroll
+  for (int gi = 0; gi < GM; ++gi) {
+    const int g = threadIdx.x + gi * 256;
+    if (g < nG) {
+      const int t = TFAST ? (g & ((1 << lgT) - 1)) : (g >> lgJ);
+      const int j = TFAST ? (g >> lgT) : (g & ((1 << lgJ) - 1));
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[gi][r] = buf[addr(t, j + (r << lgJ))];
+      if (lgNs > 0) {
+        const int k = j & ((1 << lgNs) - 1);
+        const int sh = 12 - lgNs - LGR;
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[gi][r] = cmul(v[gi][r], tab[(r * k) << sh]);
+      }
+      dft_inv<LGR>(v[gi]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int gi = 0; gi < GM; ++gi) {
+    const int g = threadIdx.x + gi * 256;
+    if (g < nG) {
+      const int t = TFAST ? (g & ((1 << lgT) - 1)) : (g >> lgJ);
+      const int j = TFAST ? (g >> lgT) : (g & ((1 << lgJ) - 1));
+      const int k = j & ((1 << lgNs) - 1);
+      const int d = ((j >> lgNs) << (lgNs + LGR)) + k;
+#pragma unroll
+      for (int s = 0; s < R; ++s) buf[addr(t, d + (s << lgNs))] = v[gi][s];
+    }
+  }
+  __syncthreads();
+}
+
+// In-place inverse DFTs (natural order in and out) of the 2^lgT
+// transforms of length 2^lgL (<= 4096) in buf.
+template <int EMAX, bool TFAST, class Addr>
+__device__ void fft_inv(float2* buf, Addr addr, int lgL, int lgT,
+                        const float2* __restrict__ tab) {
+  int lgNs = 0;
+  while (lgL - lgNs >= 4) {
+    stockham_pass<4, EMAX, TFAST>(buf, addr, lgL, lgT, lgNs, tab);
+    lgNs += 4;
+  }
+  switch (lgL - lgNs) {
+    case 1: stockham_pass<1, EMAX, TFAST>(buf, addr, lgL, lgT, lgNs, tab); break;
+    case 2: stockham_pass<2, EMAX, TFAST>(buf, addr, lgL, lgT, lgNs, tab); break;
+    case 3: stockham_pass<3, EMAX, TFAST>(buf, addr, lgL, lgT, lgNs, tab); break;
+    default: break;
   }
 }
 
@@ -91,50 +201,24 @@ __device__ __forceinline__ void store_out(const PinkArgs& a, int64_t series,
   }
 }
 
+// padded pass-1 buffer: two transforms of up to 4096
+constexpr int kPass1Buf = 2 * kLdsC + (2 * kLdsC >> 4);
+
 }  // namespace
 
-// In-place inverse DFT of one transform of length 2^lg, natural-order
-// input, bit-reversed output (decimation in frequency).
-__device__ void lds_dif(float2* buf, const float2* __restrict__ tws, int lg) {
-  if (lg == 0) return;
-  const int half_total = 1 << (lg - 1);
-  for (int s = lg; s >= 1; --s) {
-    const int half = 1 << (s - 1);
-    const float2* tw = tws + (half - 1);
-    for (int bf = threadIdx.x; bf < half_total; bf += blockDim.x) {
-      const int pos = bf & (half - 1);
-      const int i = ((bf >> (s - 1)) << s) + pos;
-      const int jx = i + half;
-      const float2 u = buf[i];
-      const float2 v = buf[jx];
-      buf[i] = make_float2(u.x + v.x, u.y + v.y);
-      buf[jx] = cmul(make_float2(u.x - v.x, u.y - v.y), tw[pos]);
-    }
-    __syncthreads();
-  }
+// Twiddle table: entry m holds e^{2 pi i m / 4096}.
+__global__ void k_pink_tables(float2* tab) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m < kLdsC) tab[m] = twiddle((uint32_t)m, 12);
 }
 
 // Pass 1 works on a set of columns closed under k -> M - k: column 0,
 // column M1/2, or the pair (k1, M1 - k1).  Each spectral bin X_j is drawn
 // once; every Z_k is built from X_k and X_{M-k} held in LDS, two at a time
 // (e^{2 pi i (M-k)/N} = -conj e^{2 pi i k/N}).
-// Per-stage twiddle tables for transforms of length 2^lg: entry m lies in
-// the stage of half-length h = 2^floor(log2(m + 1)) and holds
-// e^{2 pi i (m - h + 1) / 2h}.
-__global__ void k_pink_tables(float2* tw1, int lg1, float2* tw2, int lg2) {
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  const int n1 = (1 << lg1) - 1, n2 = (1 << lg2) - 1;
-  if (m < n1 || m < n2) {
-    const int lh = 31 - __clz(m + 1);      // log2 h
-    const uint32_t pos = (uint32_t)(m + 1 - (1 << lh));
-    const float2 v = twiddle(pos, lh + 1);
-    if (m < n1) tw1[m] = v;
-    if (m < n2) tw2[m] = v;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
-  __shared__ float2 buf[2][kLdsC];
+  __shared__ float2 buf[kPass1Buf];
+  const AddrPadded at{a.lgM2};
   const int grp = blockIdx.x;
   const int sl = blockIdx.y;
   const int64_t series = a.s0 + sl;
@@ -165,7 +249,7 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
       const float cj = sc * exp2f(halpha * log2f((float)j * fstep));
       x = make_float2(cj * zc, cj * zs);
     }
-    buf[c][k2] = x;
+    buf[at(c, k2)] = x;
   }
   __syncthreads();
   // Z in place, one pair (k, M - k) per work item
@@ -182,8 +266,8 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
     } else {
       ca = 0; ra = u; cb = 1; rb = M2 - 1 - u;
     }
-    const float2 xa = buf[ca][ra];
-    const float2 xb = nyq ? make_float2(0.f, 0.f) : buf[cb][rb];
+    const float2 xa = buf[at(ca, ra)];
+    const float2 xb = nyq ? make_float2(0.f, 0.f) : buf[at(cb, rb)];
     const int64_t kk = col[ca] + (int64_t)M1 * ra;
     const float2 w = twiddle((uint32_t)kk, lgN);
     // Z_k = (X_k + conj X_{M-k}) + i w (X_k - conj X_{M-k})
@@ -192,31 +276,30 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
     const float2 wo = cmul(w, od);
     const float2 za = make_float2(ev.x - wo.y, ev.y + wo.x);
     if (nyq || (ca == cb && ra == rb)) {
-      buf[ca][ra] = za;
+      buf[at(ca, ra)] = za;
     } else {
       // Z_{M-k} with twiddle -conj(w): E' = conj(E), O' = -conj(O)
       const float2 wb = make_float2(-w.x, w.y);
       const float2 evb = make_float2(ev.x, -ev.y);
       const float2 odb = make_float2(-od.x, od.y);
       const float2 wob = cmul(wb, odb);
-      buf[ca][ra] = za;
-      buf[cb][rb] = make_float2(evb.x - wob.y, evb.y + wob.x);
+      buf[at(ca, ra)] = za;
+      buf[at(cb, rb)] = make_float2(evb.x - wob.y, evb.y + wob.x);
     }
   }
   __syncthreads();
-  lds_dif(&buf[0][0], a.tw1, a.lgM2);
-  if (ncol == 2) lds_dif(&buf[1][0], a.tw1, a.lgM2);
+  fft_inv<2 * kLdsC, false>(buf, at, a.lgM2, ncol - 1, a.tab);
   const int lgM = a.lgM1 + a.lgM2;
   for (int c = 0; c < ncol; ++c) {
     const int k1 = col[c];
     if (M1 == 1) {
       for (int m2 = threadIdx.x; m2 < M2; m2 += blockDim.x)
-        store_out(a, series, m2, buf[c][bitrev(m2, a.lgM2)]);
+        store_out(a, series, m2, buf[at(c, m2)]);
     } else {
       float2* dst = a.scratch + ((int64_t)sl * M1 + k1) * M2;
       for (int m2 = threadIdx.x; m2 < M2; m2 += blockDim.x) {
         const uint32_t e = (uint32_t)(((uint64_t)k1 * m2) & ((1ull << lgM) - 1));
-        dst[m2] = cmul(buf[c][bitrev(m2, a.lgM2)], twiddle(e, lgM));
+        dst[m2] = cmul(buf[at(c, m2)], twiddle(e, lgM));
       }
     }
   }
@@ -231,22 +314,21 @@ __global__ __launch_bounds__(256) void k_pink_pass2(PinkArgs a) {
   const int m20 = nb << lgB2;
   const float2* src = a.scratch + ((int64_t)sl << (a.lgM1 + a.lgM2));
   const int n = 1 << (a.lgM1 + lgB2);
+  // element k1 of transform bb at k1 B2 + bb: both sides consecutive
   for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
     const int k1 = idx >> lgB2, bb = idx & (B2 - 1);
-    buf[(bb << a.lgM1) + bitrev(k1, a.lgM1)] = src[(int64_t)k1 * M2 + m20 + bb];
+    buf[idx] = src[(int64_t)k1 * M2 + m20 + bb];
   }
   __syncthreads();
-  lds_dit(buf, a.tw2, a.lgM1, lgB2);
+  fft_inv<kLdsC, true>(buf, AddrInterleaved{lgB2}, a.lgM1, lgB2, a.tab);
   for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
     const int m1 = idx >> lgB2, bb = idx & (B2 - 1);
-    store_out(a, series, (int64_t)m1 * M2 + m20 + bb, buf[(bb << a.lgM1) + m1]);
+    store_out(a, series, (int64_t)m1 * M2 + m20 + bb, buf[idx]);
   }
 }
 
 void launch_pink_tables(const PinkArgs& a, hipStream_t s) {
-  const int n = 1 << std::max(a.lgM1, a.lgM2);
-  hipLaunchKernelGGL(k_pink_tables, dim3((n + 255) / 256), dim3(256), 0, s, a.tw1,
-                     a.lgM2, a.tw2, a.lgM1);
+  hipLaunchKernelGGL(k_pink_tables, dim3(kLdsC / 256), dim3(256), 0, s, a.tab_w);
 }
 
 void launch_pink_pass1(const PinkArgs& a, hipStream_t s) {

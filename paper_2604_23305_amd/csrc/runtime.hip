@@ -789,8 +789,8 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
       a.t_total = j.t_total;
       a.out_ld = j.out_ld ? j.out_ld : j.t_total;
       a.accumulate = acc;
-      a.tw1 = w->pink;
-      a.tw2 = w->pink + 4096;
+      a.tab = w->pink;
+      a.tab_w = w->pink;
       a.scratch = w->pink + kPinkTableFloat2;
       const size_t scratch_bytes = w->pink_bytes - kPinkTableFloat2 * sizeof(float2);
       const int64_t S = (int64_t)j.n_pix * f.K;
