@@ -29,10 +29,16 @@
 // read, each wave waits until at most the 5 DMAs of chunk c + 1 are in
 // flight, and a barrier makes every wave's part of chunk c visible; the
 // stage that chunk c + 2 overwrites was last read before that barrier.
+// Every LDS read of a chunk is issued before its first MFMA, so one LDS
+// latency per chunk is exposed, not one per operand group; the main loop
+// is instantiated for one and for two live 32-channel tiles, so that no
+// branch splits the reads from the MFMAs.
 //
 // Tile index -> workgroup mapping keeps the channel groups of one time tile
 // on the same XCD so the panel tile is fetched once into that XCD's L2.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "gtod_internal.h"
 #include "gemm_epilogue.h"
@@ -84,9 +90,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
   // the ring; after the loop, stage 0 holds the epilogue slices of waves
   // 0 and 1, stage 1 those of waves 2 and 3
   static_assert(kStageFloats >= 2 * kEpiWaveFloats, "epilogue LDS");
-  __shared__ float st0[kStageFloats];
-  __shared__ float st1[kStageFloats];
-  __shared__ float st2[kStageFloats];
+  __shared__ float ring[3 * kStageFloats];
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -142,54 +146,62 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
 
   const int n_chunks = a.Fp / KC;
   const int rd = wave * 32 + c;
-  // wave index and stage addresses as wave-uniform (scalar) values for M0
+  // wave index and ring address as wave-uniform (scalar) values for M0
   const int wave_s = __builtin_amdgcn_readfirstlane(wave);
-  const uint32_t lds0 = __builtin_amdgcn_readfirstlane(lds_addr(st0));
-  const uint32_t lds1 = __builtin_amdgcn_readfirstlane(lds_addr(st1));
-  const uint32_t lds2 = __builtin_amdgcn_readfirstlane(lds_addr(st2));
+  const uint32_t lds0 = __builtin_amdgcn_readfirstlane(lds_addr(ring));
   GTOD_ISSUE(lds0, 0)
-  if (n_chunks > 1) GTOD_ISSUE(lds1, 1)
-  // one chunk: SR the stage read now, SW the stage chunk kc + 2 goes to
-#define GTOD_STEP(SR, SW, kc)                                                  \
-  {                                                                            \
-    if ((kc) + 1 < n_chunks) { GTOD_WAIT_VM(5); } else { GTOD_WAIT_VM(0); }    \
-    __builtin_amdgcn_s_barrier();                                              \
-    if ((kc) + 2 < n_chunks) GTOD_ISSUE(SW, (kc) + 2)                           \
-    const float* sD = (SR);                                                    \
-    const float* sB = (SR) + MT * KC;                                          \
-    _Pragma("unroll") for (int hs = 0; hs < 2; ++hs) {                         \
-      const int q = 2 * h + hs;                                                \
-      const float4 dv = *reinterpret_cast<const float4*>(&sD[rd * KC + 4 * (q ^ swz(rd))]); \
-      float dsq[4];                                                            \
-      _Pragma("unroll") for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = dv[s4] * dv[s4]; \
-      _Pragma("unroll") for (int i = 0; i < 2; ++i) {                          \
-        if (live[i]) {                                                         \
-          float4 bv[3];                                                        \
-          _Pragma("unroll") for (int m = 0; m < 3; ++m) {                      \
-            const int rb = m * NT + i * 32 + c;                                \
-            bv[m] = *reinterpret_cast<const float4*>(&sB[rb * KC + 4 * (q ^ swz(rb))]); \
-          }                                                                    \
-          _Pragma("unroll") for (int s4 = 0; s4 < 4; ++s4) {                   \
-            acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[0][s4], dv[s4], acc[0][i][0], 0, 0, 0); \
-            acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[1][s4], dv[s4], acc[1][i][0], 0, 0, 0); \
-            acc[2][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[2][s4], dsq[s4], acc[2][i][0], 0, 0, 0); \
-          }                                                                    \
-        }                                                                      \
-      }                                                                        \
-    }                                                                          \
-  }
-  for (int kc = 0; kc < n_chunks; kc += 3) {
-    GTOD_STEP(st0, lds2, kc)
-    if (kc + 1 < n_chunks) GTOD_STEP(st1, lds0, kc + 1)
-    if (kc + 2 < n_chunks) GTOD_STEP(st2, lds1, kc + 2)
-  }
+  if (n_chunks > 1) GTOD_ISSUE(lds0 + 4u * kStageFloats, 1)
+  // NI live 32-channel tiles (uniform over the workgroup): every LDS read
+  // of a chunk is issued before its MFMAs
+  auto run = [&](auto ni_c) {
+    constexpr int NI = decltype(ni_c)::value;
+    int sr = 0;   // stage of chunk kc
+    for (int kc = 0; kc < n_chunks; ++kc) {
+      if (kc + 1 < n_chunks) { GTOD_WAIT_VM(5); } else { GTOD_WAIT_VM(0); }
+      __builtin_amdgcn_s_barrier();
+      const int sw = sr == 0 ? 2 : sr - 1;   // stage of chunk kc + 2
+      if (kc + 2 < n_chunks) GTOD_ISSUE(lds0 + 4u * kStageFloats * sw, kc + 2)
+      const float* sD = ring + kStageFloats * sr;
+      const float* sB = sD + MT * KC;
+      float4 dv[2], bv[2][NI][3];
+#pragma unroll
+      for (int hs = 0; hs < 2; ++hs) {
+        const int q = 2 * h + hs;
+        dv[hs] = *reinterpret_cast<const float4*>(&sD[rd * KC + 4 * (q ^ swz(rd))]);
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int m = 0; m < 3; ++m) {
+            const int rb = m * NT + i * 32 + c;
+            bv[hs][i][m] = *reinterpret_cast<const float4*>(&sB[rb * KC + 4 * (q ^ swz(rb))]);
+          }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int hs = 0; hs < 2; ++hs) {
+        float dsq[4];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = dv[hs][s4] * dv[hs][s4];
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+#pragma unroll
+          for (int s4 = 0; s4 < 4; ++s4) {
+            acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[hs][i][0][s4], dv[hs][s4], acc[0][i][0], 0, 0, 0);
+            acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[hs][i][1][s4], dv[hs][s4], acc[1][i][0], 0, 0, 0);
+            acc[2][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[hs][i][2][s4], dsq[s4], acc[2][i][0], 0, 0, 0);
+          }
+      }
+      sr = sr == 2 ? 0 : sr + 1;
+    }
+  };
+  if (live[1]) run(std::integral_constant<int, 2>{});
+  else run(std::integral_constant<int, 1>{});
   __syncthreads();   // every wave is done with the ring before the epilogue reuses it
-  float* const spk = (wave < 2 ? st0 : st1) + (wave & 1) * kEpiWaveFloats;
+  float* const spk = ring + (wave >> 1) * kStageFloats + (wave & 1) * kEpiWaveFloats;
   contraction_epilogue<2, 1>(a, acc, spk, row0 + wave * 32, ch0, live);
 }
 #undef GTOD_WAIT_VM
 #undef GTOD_ISSUE
-#undef GTOD_STEP
 
 void launch_gemm_f32(const GemmArgs& a0, hipStream_t s) {
   GemmArgs a = a0;
