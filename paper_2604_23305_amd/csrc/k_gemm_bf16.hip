@@ -14,10 +14,14 @@
 // dP is split once per workgroup, when a chunk is staged into LDS; the
 // response halves come pre-split from the spectral setup.
 // Workgroup: 128 samples x 64 channels, 4 waves along time, each 32
-// samples x both 32-channel tiles (96 accumulator registers, 194 VGPRs in
+// samples x both 32-channel tiles (96 accumulator registers, 230 VGPRs in
 // all), so two workgroups share a CU and hide each other's barriers and
-// epilogues.
+// epilogues.  The 13 LDS reads of an MFMA step are issued before its 14
+// MFMAs; the loop is instantiated for one and for two live channel tiles
+// so that no branch separates them.
 #include <hip/hip_runtime.h>
+
+#include <type_traits>
 
 #include "gtod_internal.h"
 #include "gemm_epilogue.h"
@@ -127,44 +131,47 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
   for (int i = 0; i < 2; ++i) live[i] = (ch0 + i * 32) < a.K;
 
   GTOD_LOAD_CHUNK(0)
-  for (int k0 = 0; k0 < a.Fp; k0 += KC) {
-    __syncthreads();
-    GTOD_STORE_CHUNK
-    __syncthreads();
-    if (k0 + KC < a.Fp) { GTOD_LOAD_CHUNK(k0 + KC) }
+  // NI live 32-channel tiles (uniform over the workgroup): the LDS reads
+  // of an MFMA step are all issued before its MFMAs
+  auto run = [&](auto ni_c) {
+    constexpr int NI = decltype(ni_c)::value;
+    for (int k0 = 0; k0 < a.Fp; k0 += KC) {
+      __syncthreads();
+      GTOD_STORE_CHUNK
+      __syncthreads();
+      if (k0 + KC < a.Fp) { GTOD_LOAD_CHUNK(k0 + KC) }
 #pragma unroll
-    for (int s = 0; s < KC / 16; ++s) {
-      const int col = 16 * s + 8 * h;
-      bf16x8 dh[1], dl[1], ds[1];
-      {
+      for (int s = 0; s < KC / 16; ++s) {
+        const int col = 16 * s + 8 * h;
         const int o = (wave * 32 + c) * LPB + col;
-        dh[0] = *reinterpret_cast<const bf16x8*>(&sD[o]);
-        dl[0] = *reinterpret_cast<const bf16x8*>(&sD[MT * LPB + o]);
-        ds[0] = *reinterpret_cast<const bf16x8*>(&sD[2 * MT * LPB + o]);
-      }
+        const bf16x8 dh = *reinterpret_cast<const bf16x8*>(&sD[o]);
+        const bf16x8 dl = *reinterpret_cast<const bf16x8*>(&sD[MT * LPB + o]);
+        const bf16x8 ds = *reinterpret_cast<const bf16x8*>(&sD[2 * MT * LPB + o]);
+        // planes: 0 B0hi, 1 B0lo, 2 B1hi, 3 B1lo, 4 B2hi
+        bf16x8 bp[NI][5];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        if (live[i]) {
-        const int ob = (i * 32 + c) * LPB + col;
-        const bf16x8 b0h = *reinterpret_cast<const bf16x8*>(&sB[0 * NT * LPB + ob]);
-        const bf16x8 b0l = *reinterpret_cast<const bf16x8*>(&sB[1 * NT * LPB + ob]);
-        const bf16x8 b1h = *reinterpret_cast<const bf16x8*>(&sB[2 * NT * LPB + ob]);
-        const bf16x8 b1l = *reinterpret_cast<const bf16x8*>(&sB[3 * NT * LPB + ob]);
-        const bf16x8 b2h = *reinterpret_cast<const bf16x8*>(&sB[4 * NT * LPB + ob]);
+        for (int i = 0; i < NI; ++i) {
+          const int ob = (i * 32 + c) * LPB + col;
 #pragma unroll
-        for (int j = 0; j < 1; ++j) {
-          acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0l, dh[j], acc[0][i][j], 0, 0, 0);
-          acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0h, dl[j], acc[0][i][j], 0, 0, 0);
-          acc[0][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b0h, dh[j], acc[0][i][j], 0, 0, 0);
-          acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1l, dh[j], acc[1][i][j], 0, 0, 0);
-          acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1h, dl[j], acc[1][i][j], 0, 0, 0);
-          acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b1h, dh[j], acc[1][i][j], 0, 0, 0);
-          acc[2][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(b2h, ds[j], acc[2][i][j], 0, 0, 0);
+          for (int pl = 0; pl < 5; ++pl)
+            bp[i][pl] = *reinterpret_cast<const bf16x8*>(&sB[pl * NT * LPB + ob]);
         }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+          acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bp[i][1], dh, acc[0][i][0], 0, 0, 0);
+          acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bp[i][0], dl, acc[0][i][0], 0, 0, 0);
+          acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bp[i][0], dh, acc[0][i][0], 0, 0, 0);
+          acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bp[i][3], dh, acc[1][i][0], 0, 0, 0);
+          acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bp[i][2], dl, acc[1][i][0], 0, 0, 0);
+          acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bp[i][2], dh, acc[1][i][0], 0, 0, 0);
+          acc[2][i][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bp[i][4], ds, acc[2][i][0], 0, 0, 0);
         }
       }
     }
-  }
+  };
+  if (live[1]) run(std::integral_constant<int, 2>{});
+  else run(std::integral_constant<int, 1>{});
 
   contraction_epilogue<2, 1>(a, acc, smem + wave * kEpiWaveFloats, row0 + wave * 32, ch0, live);
 }
