@@ -50,7 +50,19 @@ struct PanelArgs {
   float* pwv_out;        // [n_pix_job][out_ld] or null
   int64_t out_t0, out_ld;
   unsigned long long* counters;  // [2]
+  // Row order.  With a source cube the rows are processed grouped by the
+  // source cell they read (a counting sort on key = coarse cell, last
+  // bucket = no source), so that rows sharing cube corners run together.
+  void* rinfo;           // [n_pix*Tpad] per-row quantities (RowInfo)
+  uint32_t* key;         // [n_pix*Tpad] bucket of each row
+  uint32_t* order;       // [n_pix*Tpad] rows grouped by bucket
+  uint32_t* hist;        // [n_buckets] counts, then running offsets
+  int n_buckets;         // coarse cells + 1; 1 = no sort
+  int cell_shift;        // coarse cell = (el cell >> s, az cell >> s)
+  int n_az_coarse;
 };
+constexpr int kPanelRowInfoBytes = 48;   // sizeof(RowInfo) rounded up
+constexpr int kPanelMaxBuckets = 1 << 16;
 
 struct GemmArgs {
   const float* panel;    // [rows][Fp] deviations dP

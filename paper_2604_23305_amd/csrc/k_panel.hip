@@ -13,6 +13,14 @@
 //   dP    = P - Pref
 // A workgroup handles kPanelRows rows; threads stride over nu so that every
 // table, cube and panel access is a contiguous run along nu.
+//
+// With a source cube, a scan that moves a cell or more per sample makes
+// consecutive samples read different cube corners (four spectra of F
+// floats each), which then come from beyond the L2 for almost every row.
+// The rows of a chunk are therefore first bucketed by the (coarse) cube
+// cell they read, with a counting sort, and the workgroups take them in
+// bucket order: rows that share corners run together.  Each row's result
+// does not depend on the order, only the cache traffic does.
 #include <hip/hip_runtime.h>
 
 #include "gtod_internal.h"
@@ -31,6 +39,7 @@ struct RowInfo {
   float wa, we;    // source weights along az / el
   int64_t sbase;   // offset of corner (el, az) in the cube
 };
+static_assert(sizeof(RowInfo) <= kPanelRowInfoBytes, "row record");
 
 __device__ inline void clamp_cell(double g, int64_t n, int64_t* cell,
                                   double* w, bool* clamped) {
@@ -42,69 +51,69 @@ __device__ inline void clamp_cell(double g, int64_t n, int64_t* cell,
   *w = gc - (double)c;
 }
 
-}  // namespace
-
-__global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
-  __shared__ RowInfo ri[kPanelRows];
-  const int64_t row0 = (int64_t)blockIdx.x * kPanelRows;
-
-  if (threadIdx.x < kPanelRows) {
-    RowInfo q{};
-    const int64_t r = row0 + threadIdx.x;
-    const int pl = (int)(r / a.Tpad);
-    const int tl = (int)(r % a.Tpad);
-    q.valid = (pl < a.n_pix) && (tl < a.Tc);
-    if (q.valid) {
-      const int p = a.p0 + pl;
-      const int64_t n = a.t0 + tl;
-      const double t = (double)n / a.f_s;
-      double phi, th;
-      scan_offsets(a.scan_kind, a.r_petal, a.omega, a.Omega, a.traj, n, a.f_s,
-                   &phi, &th);
-      const double x = a.h * tan(phi + a.dphi[p]) + a.wind * t;
-      const double y = a.h * tan(th + a.dtheta[p]);
-      int64_t cx, cy;
-      double wx, wy;
-      bool ox, oy;
-      clamp_cell(x / a.dx + a.ix0, a.nx, &cx, &wx, &ox);
-      clamp_cell(y / a.dy + a.iy0, a.ny, &cy, &wy, &oy);
-      const double* s0 = a.scr + cy * a.nx + cx;
-      const double pwv = (1.0 - wx) * (1.0 - wy) * s0[0] + wx * (1.0 - wy) * s0[1] +
-                         (1.0 - wx) * wy * s0[a.nx] + wx * wy * s0[a.nx + 1];
-      if (ox || oy) atomicAdd(&a.counters[0], 1ull);
-      if (a.pwv_out) a.pwv_out[(int64_t)p * a.out_ld + (n - a.out_t0)] = (float)pwv;
-      int64_t li;
-      double lw;
-      bool ol;
-      clamp_cell((pwv - a.pwv0) / a.dpwv, a.n_pwv, &li, &lw, &ol);
-      if (ol) atomicAdd(&a.counters[1], 1ull);
-      q.li = (int)li;
-      q.lw = (float)lw;
-      const double el = th + a.theta0 + a.dtheta[p];
-      q.csc = (float)(1.0 / sin(el));
-      q.src = 0;
-      if (a.cube) {
-        const double az = phi + a.phi0 + a.dphi[p];
-        const double ga = (az - a.az0) / a.daz;
-        const double ge = (el - a.el0) / a.del;
-        if (ga >= 0.0 && ga <= (double)(a.n_az - 1) && ge >= 0.0 &&
-            ge <= (double)(a.n_el - 1)) {
-          int64_t ca, ce;
-          double wa, we;
-          bool d0, d1;
-          clamp_cell(ga, a.n_az, &ca, &wa, &d0);
-          clamp_cell(ge, a.n_el, &ce, &we, &d1);
-          q.src = 1;
-          q.wa = (float)wa;
-          q.we = (float)we;
-          q.sbase = (ce * a.n_az + ca) * a.cube_ld;
-        }
-      }
+// Row quantities of row r (FP64 geometry), the PWV output and the clamp
+// counters; *bucket gets the row's sort bucket.
+__device__ RowInfo row_info(const PanelArgs& a, int64_t r, uint32_t* bucket) {
+  RowInfo q{};
+  *bucket = (uint32_t)(a.n_buckets - 1);
+  const int pl = (int)(r / a.Tpad);
+  const int tl = (int)(r % a.Tpad);
+  q.valid = (pl < a.n_pix) && (tl < a.Tc);
+  if (!q.valid) return q;
+  const int p = a.p0 + pl;
+  const int64_t n = a.t0 + tl;
+  const double t = (double)n / a.f_s;
+  double phi, th;
+  scan_offsets(a.scan_kind, a.r_petal, a.omega, a.Omega, a.traj, n, a.f_s,
+               &phi, &th);
+  const double x = a.h * tan(phi + a.dphi[p]) + a.wind * t;
+  const double y = a.h * tan(th + a.dtheta[p]);
+  int64_t cx, cy;
+  double wx, wy;
+  bool ox, oy;
+  clamp_cell(x / a.dx + a.ix0, a.nx, &cx, &wx, &ox);
+  clamp_cell(y / a.dy + a.iy0, a.ny, &cy, &wy, &oy);
+  const double* s0 = a.scr + cy * a.nx + cx;
+  const double pwv = (1.0 - wx) * (1.0 - wy) * s0[0] + wx * (1.0 - wy) * s0[1] +
+                     (1.0 - wx) * wy * s0[a.nx] + wx * wy * s0[a.nx + 1];
+  if (ox || oy) atomicAdd(&a.counters[0], 1ull);
+  if (a.pwv_out) a.pwv_out[(int64_t)p * a.out_ld + (n - a.out_t0)] = (float)pwv;
+  int64_t li;
+  double lw;
+  bool ol;
+  clamp_cell((pwv - a.pwv0) / a.dpwv, a.n_pwv, &li, &lw, &ol);
+  if (ol) atomicAdd(&a.counters[1], 1ull);
+  q.li = (int)li;
+  q.lw = (float)lw;
+  const double el = th + a.theta0 + a.dtheta[p];
+  q.csc = (float)(1.0 / sin(el));
+  q.src = 0;
+  if (a.cube) {
+    const double az = phi + a.phi0 + a.dphi[p];
+    const double ga = (az - a.az0) / a.daz;
+    const double ge = (el - a.el0) / a.del;
+    if (ga >= 0.0 && ga <= (double)(a.n_az - 1) && ge >= 0.0 &&
+        ge <= (double)(a.n_el - 1)) {
+      int64_t ca, ce;
+      double wa, we;
+      bool d0, d1;
+      clamp_cell(ga, a.n_az, &ca, &wa, &d0);
+      clamp_cell(ge, a.n_el, &ce, &we, &d1);
+      q.src = 1;
+      q.wa = (float)wa;
+      q.we = (float)we;
+      q.sbase = (ce * a.n_az + ca) * a.cube_ld;
+      if (a.n_buckets > 1)
+        *bucket = (uint32_t)((ce >> a.cell_shift) * a.n_az_coarse + (ca >> a.cell_shift));
     }
-    ri[threadIdx.x] = q;
   }
-  __syncthreads();
+  return q;
+}
 
+// dP of kPanelRows rows (records in LDS) over every bin; rows[rr] is the
+// panel row record rr goes to.
+__device__ __forceinline__ void panel_rows(const PanelArgs& a, const RowInfo* ri,
+                                           const int64_t* rows) {
   const int64_t Fp = a.Fp;
   for (int j = threadIdx.x; j < a.Fp; j += blockDim.x) {
     const bool inF = j < a.F;
@@ -129,15 +138,105 @@ __global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
         }
         dP = P - Pr;
       }
-      a.panel[(row0 + rr) * Fp + j] = dP;
+      a.panel[rows[rr] * Fp + j] = dP;
     }
   }
+}
+
+}  // namespace
+
+// Unsorted panel: workgroup b computes rows 32 b .. 32 b + 31 (one pixel,
+// consecutive samples); the first 32 threads derive the row records.
+__global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
+  __shared__ RowInfo ri[kPanelRows];
+  __shared__ int64_t rows[kPanelRows];
+  const int64_t row0 = (int64_t)blockIdx.x * kPanelRows;
+  if (threadIdx.x < kPanelRows) {
+    uint32_t bucket;
+    ri[threadIdx.x] = row_info(a, row0 + threadIdx.x, &bucket);
+    rows[threadIdx.x] = row0 + threadIdx.x;
+  }
+  __syncthreads();
+  panel_rows(a, ri, rows);
+}
+
+// Sorted panel, step 1: one thread per row writes its record and bucket
+// and counts the bucket.
+__global__ __launch_bounds__(256) void k_panel_info(PanelArgs a) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)a.n_pix * a.Tpad) return;
+  uint32_t bucket;
+  const RowInfo q = row_info(a, r, &bucket);
+  reinterpret_cast<RowInfo*>(a.rinfo)[r] = q;
+  a.key[r] = bucket;
+  atomicAdd(&a.hist[bucket], 1u);
+}
+
+// Step 2: exclusive prefix sum of the bucket counts, in place (one
+// workgroup of 1024 threads, 1024 buckets per round).
+__global__ __launch_bounds__(1024) void k_panel_scan(uint32_t* hist, int n) {
+  __shared__ uint32_t sh[1024];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  for (int base = 0; base < n; base += 1024) {
+    const int i = base + threadIdx.x;
+    const uint32_t v = i < n ? hist[i] : 0u;
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const uint32_t u = threadIdx.x >= off ? sh[threadIdx.x - off] : 0u;
+      __syncthreads();
+      sh[threadIdx.x] += u;
+      __syncthreads();
+    }
+    if (i < n) hist[i] = carry + sh[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += sh[1023];
+    __syncthreads();
+  }
+}
+
+// Step 3: scatter the row indices into bucket order.
+__global__ __launch_bounds__(256) void k_panel_scatter(PanelArgs a) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= (int64_t)a.n_pix * a.Tpad) return;
+  const uint32_t pos = atomicAdd(&a.hist[a.key[r]], 1u);
+  a.order[pos] = (uint32_t)r;
+}
+
+// Step 4: workgroup b computes the 32 rows at positions 32 b .. 32 b + 31
+// of the bucket order.
+__global__ __launch_bounds__(256) void k_panel_sorted(PanelArgs a) {
+  __shared__ RowInfo ri[kPanelRows];
+  __shared__ int64_t rows[kPanelRows];
+  if (threadIdx.x < kPanelRows) {
+    const int64_t r = a.order[(int64_t)blockIdx.x * kPanelRows + threadIdx.x];
+    ri[threadIdx.x] = reinterpret_cast<const RowInfo*>(a.rinfo)[r];
+    rows[threadIdx.x] = r;
+  }
+  __syncthreads();
+  panel_rows(a, ri, rows);
+}
+
+__global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 void launch_panel(const PanelArgs& a, hipStream_t s) {
   const int64_t rows = (int64_t)a.n_pix * a.Tpad;
   const int64_t blocks = rows / kPanelRows;
-  hipLaunchKernelGGL(k_panel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+  if (a.n_buckets <= 1) {
+    hipLaunchKernelGGL(k_panel, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return;
+  }
+  const unsigned rb = (unsigned)((rows + 255) / 256);
+  hipLaunchKernelGGL(k_fill_u32, dim3((a.n_buckets + 255) / 256), dim3(256), 0, s,
+                     a.hist, a.n_buckets, 0u);
+  hipLaunchKernelGGL(k_panel_info, dim3(rb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_panel_scan, dim3(1), dim3(1024), 0, s, a.hist, a.n_buckets);
+  hipLaunchKernelGGL(k_panel_scatter, dim3(rb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_panel_sorted, dim3((unsigned)blocks), dim3(256), 0, s, a);
 }
 
 }  // namespace gtod

@@ -811,7 +811,25 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
     const ScreenObj& sc = *plan[i].scr;
     const int64_t T = j.t_end - j.t_begin;
     if (T == 0) continue;
-    const int64_t rows_cap = (int64_t)(w->panel_bytes / ((size_t)f.Fp * 4));
+    // with a source cube the rows are bucketed by coarse cube cell (at most
+    // kPanelMaxBuckets cells); each row then also needs a record, a key and
+    // an order slot beside its panel row
+    int n_buckets = 1, cell_shift = 0, n_az_c = 0;
+    if (j.cube) {
+      for (;; ++cell_shift) {
+        const int64_t ne = ((int64_t)j.n_el + (1 << cell_shift) - 1) >> cell_shift;
+        const int64_t na = ((int64_t)j.n_az + (1 << cell_shift) - 1) >> cell_shift;
+        if (ne * na <= kPanelMaxBuckets) {
+          n_buckets = (int)(ne * na) + 1;
+          n_az_c = (int)na;
+          break;
+        }
+      }
+    }
+    const int64_t per_row = (int64_t)f.Fp * 4 + (n_buckets > 1 ? kPanelRowInfoBytes + 8 : 0);
+    const int64_t hist_bytes = round_up((int64_t)n_buckets * 4, 256);
+    const int64_t rows_cap = std::max<int64_t>(
+        0, ((int64_t)w->panel_bytes - hist_bytes - 4 * 256) / per_row);
     int pg;          // pixels per chunk
     int64_t Tc_max;  // samples per chunk
     if ((int64_t)j.n_pix * kRowPad <= rows_cap) {
@@ -867,6 +885,19 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
     pa.out_t0 = j.out_ld ? j.out_t0 : 0;
     pa.out_ld = j.out_ld ? j.out_ld : j.t_total;
     pa.counters = c->counters;
+    pa.n_buckets = n_buckets;
+    pa.cell_shift = cell_shift;
+    pa.n_az_coarse = n_az_c;
+    if (n_buckets > 1) {
+      char* aux = (char*)w->panel + round_up(rows_cap * f.Fp * 4, 256);
+      pa.rinfo = aux;
+      aux += round_up(rows_cap * kPanelRowInfoBytes, 256);
+      pa.key = (uint32_t*)aux;
+      aux += round_up(rows_cap * 4, 256);
+      pa.order = (uint32_t*)aux;
+      aux += round_up(rows_cap * 4, 256);
+      pa.hist = (uint32_t*)aux;
+    }
     GemmArgs ga{};
     ga.panel = w->panel;
     ga.B = f.B;
