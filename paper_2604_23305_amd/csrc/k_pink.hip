@@ -26,8 +26,12 @@
 // does the length-R DFT in registers and stores output s at
 // (j div S) S R + (j mod S) + s S.  Input and output are in natural order.
 // Pass twiddles come from one table of e^{2 pi i m / 4096} in global
-// memory (evaluated with sincospi on exact arguments); the in-register
-// DFTs use the constants cos, sin(2 pi m / 16).  Pass 1 keeps its one or
+// memory (evaluated with sincospi on exact arguments): a pass loads w, w^2,
+// w^4, w^8 for its group and forms the other powers as products of at
+// most four of them.  The in-register DFTs use the constants cos, sin(2 pi
+// m / 16).  The real-to-complex and four-step twiddles of a thread's 16
+// elements are a geometric sequence, taken as w0 times products of at most
+// four sincospi factors.  Pass 1 keeps its one or
 // two transforms contiguous in LDS with one float2 of padding after every
 // 16, so that the stride-16 stores of the first pass hit distinct banks;
 // pass 2 interleaves its B2 transforms (element i of transform t at
@@ -63,6 +67,26 @@ __device__ __forceinline__ float2 twiddle(uint32_t num, int lg_den) {
   sincospif(x, &s, &c);
   return make_float2(c, s);
 }
+
+// e^{2 pi i (e0 + i d) / 2^lg} for i = 0 .. 15: w0 times the product of the
+// factors e^{2 pi i 2^b d / 2^lg} for the set bits b of i, each evaluated
+// with sincospi on an exact argument (at most five roundings in all).
+struct GeoTwiddle {
+  float2 w0, f[4];
+  __device__ GeoTwiddle(uint32_t e0, uint32_t d, int lg) {
+    const uint32_t mask = (1u << lg) - 1;
+    w0 = twiddle(e0 & mask, lg);
+#pragma unroll
+    for (int b = 0; b < 4; ++b) f[b] = twiddle((d << b) & mask, lg);
+  }
+  __device__ float2 operator()(int i) const {
+    float2 w = w0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if ((i >> b) & 1) w = cmul(w, f[b]);
+    return w;
+  }
+};
 
 // cos and sin of 2 pi m / 16, m = 0 .. 7, rounded to float
 __device__ constexpr float kCos16[8] = {
@@ -147,10 +171,19 @@ __device__ __forceinline__ void stockham_pass(float2* buf, Addr addr, int lgL, i
 #pragma unroll
       for (int r = 0; r < R; ++r) v[gi][r] = buf[addr(t, j + (r << lgJ))];
       if (lgNs > 0) {
+        // w^r for w = e^{2 pi i k / (S R)}: w^1, w^2, w^4, w^8 from the
+        // table, the other powers as products of at most four of them
         const int k = j & ((1 << lgNs) - 1);
         const int sh = 12 - lgNs - LGR;
+        float2 wp[R];
+        wp[0] = make_float2(1.f, 0.f);
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[gi][r] = cmul(v[gi][r], tab[(r * k) << sh]);
+        for (int b = 0; b < LGR; ++b) wp[1 << b] = tab[(k << b) << sh];
+#pragma unroll
+        for (int r = 3; r < R; ++r)
+          if (r & (r - 1)) wp[r] = cmul(wp[r & (r - 1)], wp[r & -r]);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[gi][r] = cmul(v[gi][r], wp[r]);
       }
       dft_inv<LGR>(v[gi]);
     }
@@ -254,7 +287,10 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
   __syncthreads();
   // Z in place, one pair (k, M - k) per work item
   const int U = kind == 0 ? M2 / 2 + 1 : (kind == 1 ? M2 / 2 : M2);
-  for (int u = threadIdx.x; u < U; u += blockDim.x) {
+  // e^{2 pi i k / N} at k = col + M1 u, u = threadIdx.x + 256 i
+  const GeoTwiddle wz((uint32_t)(col[0] + (int64_t)M1 * threadIdx.x),
+                      (uint32_t)((int64_t)M1 * 256), lgN);
+  for (int u = threadIdx.x, iu = 0; u < U; u += 256, ++iu) {
     int ca, ra, cb, rb;   // (column slot, row) of k and of M - k
     bool nyq = false;
     if (kind == 0) {
@@ -268,8 +304,7 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
     }
     const float2 xa = buf[at(ca, ra)];
     const float2 xb = nyq ? make_float2(0.f, 0.f) : buf[at(cb, rb)];
-    const int64_t kk = col[ca] + (int64_t)M1 * ra;
-    const float2 w = twiddle((uint32_t)kk, lgN);
+    const float2 w = wz(iu);
     // Z_k = (X_k + conj X_{M-k}) + i w (X_k - conj X_{M-k})
     const float2 ev = make_float2(xa.x + xb.x, xa.y - xb.y);
     const float2 od = make_float2(xa.x - xb.x, xa.y + xb.y);
@@ -297,10 +332,11 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
         store_out(a, series, m2, buf[at(c, m2)]);
     } else {
       float2* dst = a.scratch + ((int64_t)sl * M1 + k1) * M2;
-      for (int m2 = threadIdx.x; m2 < M2; m2 += blockDim.x) {
-        const uint32_t e = (uint32_t)(((uint64_t)k1 * m2) & ((1ull << lgM) - 1));
-        dst[m2] = cmul(buf[at(c, m2)], twiddle(e, lgM));
-      }
+      // e^{2 pi i k1 m2 / M} at m2 = threadIdx.x + 256 i
+      const GeoTwiddle ws((uint32_t)((uint64_t)k1 * threadIdx.x),
+                          (uint32_t)((uint64_t)k1 * 256), lgM);
+      for (int m2 = threadIdx.x, im = 0; m2 < M2; m2 += 256, ++im)
+        dst[m2] = cmul(buf[at(c, m2)], ws(im));
     }
   }
 }
