@@ -341,8 +341,12 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
   }
 }
 
+// Pass 2 for at most EMAX = 2^(lgM1 + lgB2) elements per workgroup, held
+// in dynamic LDS of exactly that size (small blocks keep many workgroups
+// per CU, which is what this memory-bound pass needs).
+template <int EMAX>
 __global__ __launch_bounds__(256) void k_pink_pass2(PinkArgs a) {
-  __shared__ float2 buf[kLdsC];
+  extern __shared__ float2 buf[];
   const int nb = blockIdx.x;
   const int sl = blockIdx.y;
   const int64_t series = a.s0 + sl;
@@ -356,7 +360,7 @@ __global__ __launch_bounds__(256) void k_pink_pass2(PinkArgs a) {
     buf[idx] = src[(int64_t)k1 * M2 + m20 + bb];
   }
   __syncthreads();
-  fft_inv<kLdsC, true>(buf, AddrInterleaved{lgB2}, a.lgM1, lgB2, a.tab);
+  fft_inv<EMAX, true>(buf, AddrInterleaved{lgB2}, a.lgM1, lgB2, a.tab);
   for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
     const int m1 = idx >> lgB2, bb = idx & (B2 - 1);
     store_out(a, series, (int64_t)m1 * M2 + m20 + bb, buf[idx]);
@@ -373,8 +377,13 @@ void launch_pink_pass1(const PinkArgs& a, hipStream_t s) {
 }
 
 void launch_pink_pass2(const PinkArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_pink_pass2, dim3(a.M2 >> a.lgB2, a.n_series), dim3(256), 0,
-                     s, a);
+  const dim3 grid(a.M2 >> a.lgB2, a.n_series);
+  const int e = 1 << (a.lgM1 + a.lgB2);
+  const size_t lds = (size_t)e * sizeof(float2);
+  if (e <= kLdsC / 2)
+    hipLaunchKernelGGL(k_pink_pass2<kLdsC / 2>, grid, dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_pink_pass2<kLdsC>, grid, dim3(256), lds, s, a);
 }
 
 __global__ void k_philox(const uint32_t* ctr, uint32_t* out, int64_t n,

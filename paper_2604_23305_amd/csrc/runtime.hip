@@ -777,7 +777,8 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
       a.M1 = 1 << a.lgM1;
       a.M2 = 1 << a.lgM2;
       a.N = (int)N;
-      a.lgB2 = std::min(5, 12 - a.lgM1);
+      // pass-2 columns per workgroup: 16 while the block fits 2048 values
+      a.lgB2 = std::max(0, std::min(kPinkLgB2, 11 - a.lgM1));
       a.fs = c->fs;
       a.K = f.K;
       a.scale = (const float*)(ds + plan[i].off_scale);

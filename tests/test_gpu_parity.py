@@ -168,6 +168,28 @@ def test_pink_lengths(ctx, T):
             assert err <= TOL_PINK, (p, k, err)
 
 
+@pytest.mark.parametrize("T,K", [(2**21 + 5, 2), (2**25 - 3, 1)])
+def test_pink_long_series(ctx, T, K):
+    """Long series: four-step splits with 512 and with 4096 columns (the
+    longest series accepted), i.e. pass 2 with 4 columns per workgroup and
+    with a single one."""
+    sc = tiny_scenario(F=16, K=K, P=1, T=T)
+    sc.pink_alpha = np.array([1.0, 2.0])[:K]
+    run = g.ScenarioRun(ctx, sc)
+    tod = torch.zeros((1, K, T), device="cuda")
+    g.simulate_tod(ctx, [run.pink_job(tod, accumulate=False)])
+    torch.cuda.synchronize()
+    got = tod.cpu().numpy()
+    del tod
+    nep2 = oracle.tod.reference_nep2(sc)
+    A = opk.amplitude(nep2, sc.pink_alpha, 1.0)
+    for k in range(K):
+        ref = opk.series(sc.seed, 0, k, A[k], sc.pink_alpha[k], T, 160.0)
+        err = np.abs(got[0, k] - ref).max() / ref.std()
+        print(f"  T={T} k={k}: max err / rms {err:.3e}", flush=True)
+        assert err <= TOL_PINK, (k, err)
+
+
 def test_nep2_reference_matches_oracle(ctx):
     sc = configs.c2(t_total=256, screen_shape=(64, 4096))
     run = g.ScenarioRun(ctx, sc)
