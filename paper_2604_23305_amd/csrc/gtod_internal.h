@@ -112,6 +112,7 @@ struct PinkArgs {
   const float2* tab;     // [4096] e^{2 pi i m / 4096}
   float2* tab_w;         // the same table, written by k_pink_tables
 };
+constexpr int kPinkLgM2 = 11;                // log2 of the usual 1/f pass-1 length
 constexpr int kPinkLgB2 = 4;                 // log2 of the 1/f pass-2 columns per workgroup
 constexpr int kPinkTableFloat2 = 2 * 4096;   // reserved at the workspace head
 

@@ -234,8 +234,6 @@ __device__ __forceinline__ void store_out(const PinkArgs& a, int64_t series,
   }
 }
 
-// padded pass-1 buffer: two transforms of up to 4096
-constexpr int kPass1Buf = 2 * kLdsC + (2 * kLdsC >> 4);
 
 }  // namespace
 
@@ -249,8 +247,11 @@ __global__ void k_pink_tables(float2* tab) {
 // column M1/2, or the pair (k1, M1 - k1).  Each spectral bin X_j is drawn
 // once; every Z_k is built from X_k and X_{M-k} held in LDS, two at a time
 // (e^{2 pi i (M-k)/N} = -conj e^{2 pi i k/N}).
+// Dynamic LDS: one or two padded transforms of M2 values; EMAX bounds the
+// values per workgroup.
+template <int EMAX>
 __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
-  __shared__ float2 buf[kPass1Buf];
+  extern __shared__ float2 buf[];
   const AddrPadded at{a.lgM2};
   const int grp = blockIdx.x;
   const int sl = blockIdx.y;
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
     }
   }
   __syncthreads();
-  fft_inv<2 * kLdsC, false>(buf, at, a.lgM2, ncol - 1, a.tab);
+  fft_inv<EMAX, false>(buf, at, a.lgM2, ncol - 1, a.tab);
   const int lgM = a.lgM1 + a.lgM2;
   for (int c = 0; c < ncol; ++c) {
     const int k1 = col[c];
@@ -373,7 +374,13 @@ void launch_pink_tables(const PinkArgs& a, hipStream_t s) {
 
 void launch_pink_pass1(const PinkArgs& a, hipStream_t s) {
   const int groups = a.M1 == 1 ? 1 : a.M1 / 2 + 1;
-  hipLaunchKernelGGL(k_pink_pass1, dim3(groups, a.n_series), dim3(256), 0, s, a);
+  const int e = (a.M1 == 1 ? 1 : 2) << a.lgM2;   // values per workgroup
+  const size_t lds = (size_t)(e + (e >> 4)) * sizeof(float2);
+  const dim3 grid(groups, a.n_series);
+  if (e <= kLdsC)
+    hipLaunchKernelGGL(k_pink_pass1<kLdsC>, grid, dim3(256), lds, s, a);
+  else
+    hipLaunchKernelGGL(k_pink_pass1<2 * kLdsC>, grid, dim3(256), lds, s, a);
 }
 
 void launch_pink_pass2(const PinkArgs& a, hipStream_t s) {

@@ -772,13 +772,15 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
       while (N < j.t_total) N *= 2;
       const int lgM = (int)std::log2((double)(N / 2));
       a.M = (int)(N / 2);
-      a.lgM2 = std::min(lgM, 12);
+      // pass-1 transforms of 2048 (two per workgroup, 35 KB of LDS), longer
+      // only where pass 2 would exceed 4096 values per column set
+      a.lgM2 = std::max(std::min(lgM, kPinkLgM2), lgM - 12);
       a.lgM1 = lgM - a.lgM2;
       a.M1 = 1 << a.lgM1;
       a.M2 = 1 << a.lgM2;
       a.N = (int)N;
-      // pass-2 columns per workgroup: 16 while the block fits 2048 values
-      a.lgB2 = std::max(0, std::min(kPinkLgB2, 11 - a.lgM1));
+      // pass-2 columns per workgroup: 16 while the block fits 4096 values
+      a.lgB2 = std::max(0, std::min(kPinkLgB2, 12 - a.lgM1));
       a.fs = c->fs;
       a.K = f.K;
       a.scale = (const float*)(ds + plan[i].off_scale);
