@@ -111,34 +111,54 @@ __device__ RowInfo row_info(const PanelArgs& a, int64_t r, uint32_t* bucket) {
 }
 
 // dP of kPanelRows rows (records in LDS) over every bin; rows[rr] is the
-// panel row record rr goes to.
+// panel row record rr goes to.  The table and cube reads of 8 rows are
+// issued together before their arithmetic (addresses clamped into the
+// arrays, so rows without data read harmless values that are not used),
+// which keeps 48 loads per lane in flight instead of one row's.
 __device__ __forceinline__ void panel_rows(const PanelArgs& a, const RowInfo* ri,
                                            const int64_t* rows) {
+  constexpr int kB = 8;
   const int64_t Fp = a.Fp;
+  const bool with_cube = a.cube != nullptr;
+  const int64_t ld = a.cube_ld, crow = (int64_t)a.n_az * a.cube_ld;
   for (int j = threadIdx.x; j < a.Fp; j += blockDim.x) {
     const bool inF = j < a.F;
+    const int jj = inF ? j : a.F - 1;
     const float E = a.E[j], D = a.D[j], W = a.W[j], Pr = a.Pref[j];
-#pragma unroll 2
-    for (int rr = 0; rr < kPanelRows; ++rr) {
-      const RowInfo& q = ri[rr];
-      float dP = 0.f;
-      if (q.valid && inF) {
-        const float t0v = a.tau[(int64_t)q.li * Fp + j];
-        const float t1v = a.tau[(int64_t)(q.li + 1) * Fp + j];
-        const float tz = (1.f - q.lw) * t0v + q.lw * t1v;
-        const float xi = -expm1f(-q.csc * tz);
-        float P = E + xi * D;
-        if (q.src) {
-          const float* c = a.cube + q.sbase + j;
-          const int64_t ld = a.cube_ld, row = (int64_t)a.n_az * a.cube_ld;
-          const float ps = (1.f - q.wa) * (1.f - q.we) * c[0] +
-                           q.wa * (1.f - q.we) * c[ld] +
-                           (1.f - q.wa) * q.we * c[row] + q.wa * q.we * c[row + ld];
-          P += (1.f - xi) * (W * ps);
+#pragma unroll 1
+    for (int rb = 0; rb < kPanelRows; rb += kB) {
+      float t0[kB], t1[kB], cs[kB][4];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const RowInfo& q = ri[rb + u];
+        t0[u] = a.tau[(int64_t)q.li * Fp + jj];
+        t1[u] = a.tau[(int64_t)(q.li + 1) * Fp + jj];
+        if (with_cube) {
+          const float* c = a.cube + q.sbase + jj;
+          cs[u][0] = c[0];
+          cs[u][1] = c[ld];
+          cs[u][2] = c[crow];
+          cs[u][3] = c[crow + ld];
         }
-        dP = P - Pr;
       }
-      a.panel[rows[rr] * Fp + j] = dP;
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        const RowInfo& q = ri[rb + u];
+        float dP = 0.f;
+        if (q.valid && inF) {
+          const float tz = (1.f - q.lw) * t0[u] + q.lw * t1[u];
+          const float xi = -expm1f(-q.csc * tz);
+          float P = E + xi * D;
+          if (q.src) {
+            const float ps = (1.f - q.wa) * (1.f - q.we) * cs[u][0] +
+                             q.wa * (1.f - q.we) * cs[u][1] +
+                             (1.f - q.wa) * q.we * cs[u][2] + q.wa * q.we * cs[u][3];
+            P += (1.f - xi) * (W * ps);
+          }
+          dP = P - Pr;
+        }
+        a.panel[rows[rb + u] * Fp + j] = dP;
+      }
     }
   }
 }
