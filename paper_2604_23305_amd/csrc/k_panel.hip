@@ -180,6 +180,24 @@ __global__ __launch_bounds__(256) void k_panel(PanelArgs a) {
   panel_rows(a, ri, rows);
 }
 
+// hist[bucket] += 1 for every active lane; returns the lane's old value.
+// The last bucket (rows without source, padding rows) can hold most rows
+// of a chunk, so its lanes add once per wave (ballot, one atomic by the
+// first of them, rank within the wave from the mask); other buckets are
+// spread over cells and add per lane.
+__device__ __forceinline__ uint32_t bucket_add(uint32_t* hist, uint32_t bucket,
+                                               uint32_t hot) {
+  const int lane = threadIdx.x & 63;
+  const uint64_t m = __ballot(bucket == hot);
+  if (bucket != hot) return atomicAdd(&hist[bucket], 1u);
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1));
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(&hist[hot], (uint32_t)__popcll(m));
+  base = __shfl(base, leader);
+  return base + rank;
+}
+
 // Sorted panel, step 1: one thread per row writes its record and bucket
 // and counts the bucket.
 __global__ __launch_bounds__(256) void k_panel_info(PanelArgs a) {
@@ -189,7 +207,7 @@ __global__ __launch_bounds__(256) void k_panel_info(PanelArgs a) {
   const RowInfo q = row_info(a, r, &bucket);
   reinterpret_cast<RowInfo*>(a.rinfo)[r] = q;
   a.key[r] = bucket;
-  atomicAdd(&a.hist[bucket], 1u);
+  bucket_add(a.hist, bucket, (uint32_t)(a.n_buckets - 1));
 }
 
 // Step 2: exclusive prefix sum of the bucket counts, in place (one
@@ -220,7 +238,7 @@ __global__ __launch_bounds__(1024) void k_panel_scan(uint32_t* hist, int n) {
 __global__ __launch_bounds__(256) void k_panel_scatter(PanelArgs a) {
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= (int64_t)a.n_pix * a.Tpad) return;
-  const uint32_t pos = atomicAdd(&a.hist[a.key[r]], 1u);
+  const uint32_t pos = bucket_add(a.hist, a.key[r], (uint32_t)(a.n_buckets - 1));
   a.order[pos] = (uint32_t)r;
 }
 

@@ -16,6 +16,7 @@ from oracle import pink as opk
 from tests.gpu_util import new_ctx, rel_err, report, run_signal
 from tests.test_oracle_pins import tiny_scenario
 from workloads import configs
+from workloads import gen
 
 pytestmark = pytest.mark.gpu
 
@@ -82,6 +83,27 @@ def test_tiny_and_ragged_shapes(ctx, filt, shape, prec):
                        stages=configs.cascade_table2())
     ref = oracle.tod.simulate(sc)
     _, out = run_signal(ctx, sc, precision=prec)
+    _compare(sc, out, ref)
+
+
+def test_large_source_grid_coarse_buckets(ctx):
+    """A 300 x 300 source grid has more cells than the panel's row sort
+    keeps buckets (65536), so rows are bucketed by 2 x 2 cells; 7 pixels
+    sweep the grid on a daisy."""
+    from workloads.scenario import Source
+    sc = tiny_scenario(F=24, K=5, P=7, T=3000)
+    cube, gr = gen.source_cube(sc.spectral.nu_hz, 300, 60 * gen.ARCSEC, 0.0,
+                               np.pi / 3,
+                               [dict(flux_jy=np.full(24, 5.0),
+                                     fwhm_rad=10 * gen.ARCSEC),
+                                dict(flux_jy=np.full(24, 2.0),
+                                     fwhm_rad=4 * gen.ARCSEC,
+                                     off_rad=(20 * gen.ARCSEC, -15 * gen.ARCSEC))],
+                               np.pi * 25)
+    sc.source = Source(cube=cube, az0=gr["az0"], daz=gr["daz"], el0=gr["el0"],
+                       del_=gr["del_"])
+    ref = oracle.tod.simulate(sc)
+    _, out = run_signal(ctx, sc)
     _compare(sc, out, ref)
 
 
