@@ -37,7 +37,10 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 constexpr int MT = 128;
 constexpr int NT = 64;
 constexpr int KC = 32;        // bins per chunk = 2 MFMA steps of 16
-constexpr int LPB = KC + 8;   // padded LDS row in bf16 (80 bytes)
+// LDS rows are KC bf16 (64 bytes), unpadded; the 16-byte chunk q of row r
+// sits at slot q ^ swz(r), so that the 16-byte reads of 16 consecutive
+// rows at one chunk hit 16 distinct bank groups.
+__device__ __forceinline__ int swz(int row) { return ((row >> 1) ^ (row >> 2)) & 3; }
 
 }  // namespace
 
@@ -51,12 +54,12 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
   const int64_t row0 = (int64_t)tt * MT;
   const int ch0 = cg * NT;
 
-  // sD: [3][MT][LPB] dP hi, dP lo, (dP^2) hi; sB: [5][NT][LPB] B0h B0l B1h B1l B2h
-  constexpr int kStage = (3 * MT * LPB + 5 * NT * LPB) / 2;
+  // sD: [3][MT][KC] dP hi, dP lo, (dP^2) hi; sB: [5][NT][KC] B0h B0l B1h B1l B2h
+  constexpr int kStage = (3 * MT * KC + 5 * NT * KC) / 2;
   constexpr int kSmem = kStage > 4 * kEpiWaveFloats ? kStage : 4 * kEpiWaveFloats;
   __shared__ float smem[kSmem];
   __bf16* sD = reinterpret_cast<__bf16*>(smem);
-  __bf16* sB = sD + 3 * MT * LPB;
+  __bf16* sB = sD + 3 * MT * KC;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -105,16 +108,18 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
       lo_[e] = (__bf16)(x_[e] - (float)hi_[e]);                              \
       sq_[e] = (__bf16)(x_[e] * x_[e]);                                      \
     }                                                                        \
-    const int o_ = (idx >> 3) * LPB + 4 * (idx & 7);                         \
+    const int r_ = idx >> 3, q_ = (idx & 7) >> 1;                            \
+    const int o_ = r_ * KC + 8 * (q_ ^ swz(r_)) + 4 * (idx & 1);             \
     *reinterpret_cast<bf16x4*>(&sD[o_]) = hi_;                               \
-    *reinterpret_cast<bf16x4*>(&sD[MT * LPB + o_]) = lo_;                    \
-    *reinterpret_cast<bf16x4*>(&sD[2 * MT * LPB + o_]) = sq_;                \
+    *reinterpret_cast<bf16x4*>(&sD[MT * KC + o_]) = lo_;                     \
+    *reinterpret_cast<bf16x4*>(&sD[2 * MT * KC + o_]) = sq_;                 \
   }
 #define GTOD_ST_B(q, src)                                                    \
   {                                                                          \
     const int idx = tid + (q) * 256;                                         \
     const int mm = idx >> 8, rem = idx & 255;                                \
-    *reinterpret_cast<uint4*>(&sB[(mm * NT + (rem >> 2)) * LPB + 8 * (rem & 3)]) = src; \
+    const int rb_ = rem >> 2;                                                \
+    *reinterpret_cast<uint4*>(&sB[(mm * NT + rb_) * KC + 8 * ((rem & 3) ^ swz(rb_))]) = src; \
   }
 #define GTOD_LOAD_CHUNK(k0n)                                                 \
   GTOD_LD_D(0, rd0, k0n) GTOD_LD_D(1, rd1, k0n) GTOD_LD_D(2, rd2, k0n)       \
@@ -142,19 +147,20 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
       if (k0 + KC < a.Fp) { GTOD_LOAD_CHUNK(k0 + KC) }
 #pragma unroll
       for (int s = 0; s < KC / 16; ++s) {
-        const int col = 16 * s + 8 * h;
-        const int o = (wave * 32 + c) * LPB + col;
+        const int rd = wave * 32 + c;
+        const int o = rd * KC + 8 * ((2 * s + h) ^ swz(rd));
         const bf16x8 dh = *reinterpret_cast<const bf16x8*>(&sD[o]);
-        const bf16x8 dl = *reinterpret_cast<const bf16x8*>(&sD[MT * LPB + o]);
-        const bf16x8 ds = *reinterpret_cast<const bf16x8*>(&sD[2 * MT * LPB + o]);
+        const bf16x8 dl = *reinterpret_cast<const bf16x8*>(&sD[MT * KC + o]);
+        const bf16x8 ds = *reinterpret_cast<const bf16x8*>(&sD[2 * MT * KC + o]);
         // planes: 0 B0hi, 1 B0lo, 2 B1hi, 3 B1lo, 4 B2hi
         bf16x8 bp[NI][5];
 #pragma unroll
         for (int i = 0; i < NI; ++i) {
-          const int ob = (i * 32 + c) * LPB + col;
+          const int rb = i * 32 + c;
+          const int ob = rb * KC + 8 * ((2 * s + h) ^ swz(rb));
 #pragma unroll
           for (int pl = 0; pl < 5; ++pl)
-            bp[i][pl] = *reinterpret_cast<const bf16x8*>(&sB[pl * NT * LPB + ob]);
+            bp[i][pl] = *reinterpret_cast<const bf16x8*>(&sB[pl * NT * KC + ob]);
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
