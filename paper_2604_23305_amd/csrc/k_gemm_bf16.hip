@@ -14,11 +14,12 @@
 // dP is split once per workgroup, when a chunk is staged into LDS; the
 // response halves come pre-split from the spectral setup.
 // Workgroup: 128 samples x 64 channels, 4 waves along time, each 32
-// samples x both 32-channel tiles (96 accumulator registers, 230 VGPRs in
+// samples x both 32-channel tiles (96 accumulator registers, 232 VGPRs in
 // all), so two workgroups share a CU and hide each other's barriers and
 // epilogues.  The 13 LDS reads of an MFMA step are issued before its 14
 // MFMAs; the loop is instantiated for one and for two live channel tiles
-// so that no branch separates them.
+// so that no branch separates them.  LDS rows are unpadded 64-byte rows
+// with an XOR swizzle of their 16-byte chunks (44 KB per workgroup).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
