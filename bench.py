@@ -458,8 +458,9 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU; --gpus {args.gpus} is not "
-              "supported (the simulation shards by pixel or request with no "
-              "exchange; see DESIGN.md)", file=sys.stderr)
+              "supported (rows and 1/f series are independent, so the "
+              "simulation shards by pixel or by request with no exchange "
+              "between GPUs)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
