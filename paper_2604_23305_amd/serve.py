@@ -5,11 +5,16 @@ over time.  The engine
   * admits a request when its arrival time has passed and its output fits in
     the HBM budget (first come, first served; later arrivals wait behind an
     earlier one that does not fit yet);
-  * pins each admitted request to one of several HIP streams (round robin)
-    so that work of different requests runs concurrently on the device;
+  * pins each admitted request to one of several HIP streams, the one with
+    the least outstanding work (detector samples not yet issued), so that
+    work of different requests runs concurrently on the device and a small
+    request does not queue behind a large one when another stream is idle;
   * issues, per stream, one gtod_simulate_tod call holding the next sample
     chunk of every active request on that stream, keeping a bounded number
-    of calls in flight per stream;
+    of calls in flight per stream.  The jobs of a call run one after the
+    other, so they are ordered by the work their requests have left, least
+    first, and the chunks that complete a request go in a call of their own
+    ahead of the rest, so that its completion event does not wait for them;
   * records completion with device events, frees the request's memory and
     admits waiting requests as memory frees up.
 Every request first gets its 1/f job (written into its TOD), then its
@@ -69,6 +74,11 @@ class Request:
     @property
     def det_samples(self) -> int:
         return self.n_pix * self.K * self.t_total
+
+    @property
+    def remaining(self) -> int:
+        """Detector samples not yet issued."""
+        return self.n_pix * self.K * (self.t_total - self.next_t)
 
     @property
     def out_bytes(self) -> int:
@@ -174,6 +184,17 @@ class Engine:
     def _now(self) -> float:
         return time.perf_counter() - self._t0_wall
 
+    def _pick_stream(self) -> int:
+        """Stream with the least outstanding work; ties go round robin."""
+        n = len(self.streams)
+        load = [0] * n
+        for r in self.active:
+            load[r.stream_idx] += r.remaining
+        order = [(self._rr + i) % n for i in range(n)]
+        si = min(order, key=lambda i: load[i])
+        self._rr = (si + 1) % n
+        return si
+
     # ------------------------------------------------------------------
     def _admit(self, now: float):
         torch = self.torch
@@ -186,8 +207,7 @@ class Engine:
                 break
             self.pending.popleft()
             self.used += r.out_bytes
-            r.stream_idx = self._rr
-            self._rr = (self._rr + 1) % len(self.streams)
+            r.stream_idx = self._pick_stream()
             # allocate (and zero) on the request's own stream so that its
             # kernels are ordered after the fill
             alloc = torch.empty if r.pink_alpha is not None else torch.zeros
@@ -212,30 +232,38 @@ class Engine:
             q.popleft()
         if len(q) >= self.max_inflight:
             return False
-        jobs, finishing = [], []
-        for r in self.active:
-            if r.stream_idx != si or r.next_t >= r.t_total:
-                continue
+        # requests whose last chunk goes out now get a call (and completion
+        # event) of their own, ahead of the others on this stream
+        fin_jobs, rest_jobs, finishing = [], [], []
+        mine = [r for r in self.active
+                if r.stream_idx == si and r.next_t < r.t_total]
+        for r in sorted(mine, key=lambda r: (r.remaining, r.rid)):
+            a = r.next_t
+            b = min(r.t_total, a + self.chunk_len(r))
+            jobs = fin_jobs if b >= r.t_total else rest_jobs
             if getattr(r, "_need_pink", False):
                 jobs.append(self._pink_job(r))
                 r._need_pink = False
-            a = r.next_t
-            b = min(r.t_total, a + self.chunk_len(r))
             jobs.append(self._signal_job(r, a, b))
             r.next_t = b
             if np.isnan(r.t_first):
                 r.t_first = now
             if b >= r.t_total:
                 finishing.append(r)
-        if not jobs:
+        if not fin_jobs and not rest_jobs:
             return False
         stream = self.streams[si]
-        simulate_tod(self.ctx, jobs, stream)
-        ev = torch.cuda.Event(enable_timing=True)
-        ev.record(stream)
+        ev = None
+        for jobs in (fin_jobs, rest_jobs):
+            if not jobs:
+                continue
+            simulate_tod(self.ctx, jobs, stream)
+            ev = torch.cuda.Event(enable_timing=True)
+            ev.record(stream)
+            if jobs is fin_jobs:
+                for r in finishing:
+                    r.done_event = ev
         q.append(ev)
-        for r in finishing:
-            r.done_event = ev
         return True
 
     def _retire(self):
