@@ -275,8 +275,10 @@ typedef struct gtod_job {
  * gtod_simulate_tod -- enqueue n_jobs jobs on hip_stream (a hipStream_t;
  * NULL for the legacy default stream) and return without waiting.
  * All jobs are validated first; on any error nothing is enqueued.  Host
- * arrays named by the jobs are consumed before return.  Each stream gets
- * its own workspace on first use; calls on one stream run in order.
+ * arrays named by the jobs are consumed before return.  The jobs of a call
+ * run one after another, in array order.  Each stream gets its own
+ * workspace on first use, kept until the context is freed; calls on one
+ * stream run in order.
  * Errors: EINVAL, ENOTFOUND, ERANGE (STRICT_RANGE), EBUDGET (first use of
  * a stream), EDEVICE (outputs are undefined afterwards).
  */

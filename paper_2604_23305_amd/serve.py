@@ -129,11 +129,18 @@ class EngineStats:
 class Engine:
     def __init__(self, ctx, n_streams=4, hbm_budget_bytes=64 << 30,
                  chunk_rows=1 << 18, max_inflight=2, keep_outputs=False,
-                 on_done: Optional[Callable[[Request], None]] = None):
+                 on_done: Optional[Callable[[Request], None]] = None,
+                 streams=None):
+        """streams: torch.cuda.Stream objects to run on (n_streams is then
+        ignored).  The library keeps a workspace per stream for the life of
+        the context, so engines that follow one another on a context should
+        share their streams."""
         import torch
         self.torch = torch
         self.ctx = ctx
-        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.streams = list(streams) if streams is not None else [
+            torch.cuda.Stream() for _ in range(n_streams)]
+        n_streams = len(self.streams)
         self.budget = hbm_budget_bytes
         self.used = 0
         self.chunk_rows = chunk_rows

@@ -120,3 +120,9 @@ def test_finishing_chunks_go_first_in_their_own_call(monkeypatch):
         eng.inflight[1][-1]
     assert big.done_event is None and mid.done_event is None
     assert other.next_t == 0 and len(eng.inflight[1]) == 1
+
+
+def test_engine_runs_on_given_streams():
+    from paper_2604_23305_amd.serve import Engine
+    eng = Engine(None, n_streams=4, streams=["a", "b"])
+    assert eng.streams == ["a", "b"] and sorted(eng.inflight) == [0, 1]
