@@ -19,13 +19,14 @@ struct u32x4 {
 __device__ __forceinline__ u32x4 philox10(u32x4 c, uint32_t k0, uint32_t k1) {
   constexpr uint32_t kM0 = 0xD2511F53u, kM1 = 0xCD9E8D57u;
   constexpr uint32_t kW0 = 0x9E3779B9u, kW1 = 0xBB67AE85u;
+  // each 64-bit product gives both halves in one v_mad_u64_u32 (separate
+  // high and low 32-bit multiplies would take two instructions)
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
-    const uint32_t lo0 = kM0 * c.x;
-    const uint32_t hi0 = __umulhi(kM0, c.x);
-    const uint32_t lo1 = kM1 * c.z;
-    const uint32_t hi1 = __umulhi(kM1, c.z);
-    c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    const uint64_t p0 = (uint64_t)kM0 * c.x;
+    const uint64_t p1 = (uint64_t)kM1 * c.z;
+    c = u32x4{(uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1,
+              (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0};
     k0 += kW0;
     k1 += kW1;
   }
