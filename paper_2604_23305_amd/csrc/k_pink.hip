@@ -222,10 +222,26 @@ __device__ void fft_inv(float2* buf, Addr addr, int lgL, int lgT,
   }
 }
 
+// Samples 2m and 2m + 1 of a series: one 8-byte access where the pair is
+// 8-byte aligned (even row pitch, aligned output), so that a run of lanes
+// covers whole cache lines in one store; else two 4-byte accesses.
 __device__ __forceinline__ void store_out(const PinkArgs& a, int64_t series,
                                           int64_t m, float2 z) {
   const int64_t t = 2 * m;
   float* dst = a.tod + series * a.out_ld;
+  const bool pairs = ((a.out_ld & 1) == 0) && ((reinterpret_cast<uintptr_t>(a.tod) & 7) == 0);
+  if (pairs && t + 1 < a.t_total) {
+    float2* d2 = reinterpret_cast<float2*>(dst + t);
+    if (a.accumulate) {
+      float2 o = *d2;
+      o.x += z.x;
+      o.y += z.y;
+      *d2 = o;
+    } else {
+      *d2 = z;
+    }
+    return;
+  }
   if (t < a.t_total) {
     if (a.accumulate) dst[t] += z.x; else dst[t] = z.x;
   }
