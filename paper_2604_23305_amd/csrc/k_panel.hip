@@ -242,18 +242,104 @@ __global__ __launch_bounds__(256) void k_panel_scatter(PanelArgs a) {
   a.order[pos] = (uint32_t)r;
 }
 
+// *(base + boff bytes): a scalar base plus a 32-bit lane offset, which
+// the load takes as its address operands directly.
+__device__ __forceinline__ float at_byte(const float* base, uint32_t boff) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + boff);
+}
+
 // Step 4: workgroup b computes the 32 rows at positions 32 b .. 32 b + 31
-// of the bucket order.
+// of the bucket order, 4 rows at a time over all bins.
+// The order slots and row records are read at workgroup-uniform
+// addresses, so they load into scalar registers and each row's table,
+// cube and panel base address is a scalar value: an access costs the
+// lane's bin offset only.  The table and cube reads of a batch are issued
+// before its arithmetic.  Rows in bucket order mostly read the same cube
+// corners as their neighbours, and often the same table rows: such a row
+// takes the values its neighbour loaded, and a row without data loads
+// nothing.  The arithmetic per (row, bin) is that of panel_rows.
 __global__ __launch_bounds__(256) void k_panel_sorted(PanelArgs a) {
-  __shared__ RowInfo ri[kPanelRows];
-  __shared__ int64_t rows[kPanelRows];
-  if (threadIdx.x < kPanelRows) {
-    const int64_t r = a.order[(int64_t)blockIdx.x * kPanelRows + threadIdx.x];
-    ri[threadIdx.x] = reinterpret_cast<const RowInfo*>(a.rinfo)[r];
-    rows[threadIdx.x] = r;
+  constexpr int kB = 4;   // rows per batch (scalar registers)
+  const RowInfo* __restrict__ rinfo = reinterpret_cast<const RowInfo*>(a.rinfo);
+  const uint32_t* ord = a.order + (int64_t)blockIdx.x * kPanelRows;
+  const int64_t Fp = a.Fp;
+  const uint32_t F = (uint32_t)a.F;
+  const int64_t crow = (int64_t)a.n_az * a.cube_ld;
+  const uint32_t row_b = 4u * (uint32_t)Fp;          // next table row, bytes
+  const uint32_t az_b = 4u * (uint32_t)a.cube_ld;    // next azimuth cell, bytes
+#pragma unroll 1
+  for (int rb = 0; rb < kPanelRows; rb += kB) {
+    RowInfo q[kB];
+    const float* tr[kB];   // table row below the PWV
+    const float* c0[kB];   // cube corners (el, az) and (el, az + 1)
+    const float* c1[kB];   // cube corners (el + 1, az) and (el + 1, az + 1)
+    float* out[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const uint32_t r = ord[rb + u];
+      q[u] = rinfo[r];
+      tr[u] = a.tau + (int64_t)q[u].li * Fp;
+      c0[u] = a.cube + q[u].sbase;
+      c1[u] = c0[u] + crow;
+      out[u] = a.panel + (int64_t)r * Fp;
+    }
+    for (uint32_t j = threadIdx.x; j < (uint32_t)Fp; j += blockDim.x) {
+      const bool inF = j < F;
+      // byte offsets of the bin, added to the scalar base addresses
+      const uint32_t jb = 4u * j;
+      const uint32_t jjb = 4u * (inF ? j : F - 1);
+      const float E = at_byte(a.E, jb), D = at_byte(a.D, jb);
+      const float W = at_byte(a.W, jb), Pr = at_byte(a.Pref, jb);
+      float t0[kB], t1[kB], cs[kB][4];
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        // uniform branches: skip rows without data, reuse a neighbour's
+        // values where the addresses are the same
+        const bool nt = q[u].valid;
+        const bool nc = q[u].valid && q[u].src;
+        if (!nt) {
+          t0[u] = t1[u] = 0.f;
+        } else if (u > 0 && q[u - 1].valid && q[u].li == q[u - 1].li) {
+          t0[u] = t0[u - 1];
+          t1[u] = t1[u - 1];
+        } else {
+          t0[u] = at_byte(tr[u], jjb);
+          t1[u] = at_byte(tr[u], jjb + row_b);
+        }
+        if (!nc) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) cs[u][m] = 0.f;
+        } else if (u > 0 && q[u - 1].valid && q[u - 1].src &&
+                   q[u].sbase == q[u - 1].sbase) {
+#pragma unroll
+          for (int m = 0; m < 4; ++m) cs[u][m] = cs[u - 1][m];
+        } else {
+          cs[u][0] = at_byte(c0[u], jjb);
+          cs[u][1] = at_byte(c0[u], jjb + az_b);
+          cs[u][2] = at_byte(c1[u], jjb);
+          cs[u][3] = at_byte(c1[u], jjb + az_b);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kB; ++u) {
+        float dP = 0.f;
+        if (q[u].valid && inF) {
+          const float tz = (1.f - q[u].lw) * t0[u] + q[u].lw * t1[u];
+          const float xi = -expm1f(-q[u].csc * tz);
+          float P = E + xi * D;
+          if (q[u].src) {
+            const float ps = (1.f - q[u].wa) * (1.f - q[u].we) * cs[u][0] +
+                             q[u].wa * (1.f - q[u].we) * cs[u][1] +
+                             (1.f - q[u].wa) * q[u].we * cs[u][2] +
+                             q[u].wa * q[u].we * cs[u][3];
+            P += (1.f - xi) * (W * ps);
+          }
+          dP = P - Pr;
+        }
+        *reinterpret_cast<float*>(reinterpret_cast<char*>(out[u]) + jb) = dP;
+      }
+    }
   }
-  __syncthreads();
-  panel_rows(a, ri, rows);
 }
 
 __global__ void k_fill_u32(uint32_t* p, int n, uint32_t v) {
