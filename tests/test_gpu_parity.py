@@ -190,6 +190,30 @@ def test_pink_lengths(ctx, T):
             assert err <= TOL_PINK, (p, k, err)
 
 
+@pytest.mark.parametrize("T,offset", [(4096, 0), (4095, 0), (9000, 0),
+                                      (9001, 0), (9000, 1)])
+def test_pink_accumulate_adds_into_tod(ctx, T, offset):
+    """ACCUMULATE adds the 1/f series into what the TOD holds, with one
+    FP32 rounding per sample: bit-identical to the written series added on
+    the host.  Even lengths take the paired 8-byte accesses, odd lengths and
+    an output starting one float past an 8-byte boundary the 4-byte ones;
+    4096 and 4095 are one-pass transforms, 9000 and 9001 two-pass."""
+    sc = tiny_scenario(F=16, K=3, P=2, T=T)
+    sc.pink_alpha = np.array([1.0, 0.5, 2.0])
+    run = g.ScenarioRun(ctx, sc)
+    n = sc.n_pix * sc.K * T
+    written = torch.zeros((sc.n_pix, sc.K, T), device="cuda")
+    g.simulate_tod(ctx, [run.pink_job(written, accumulate=False)])
+    base = torch.randn(n, generator=torch.Generator().manual_seed(T + offset))
+    buf = torch.zeros(offset + n, device="cuda")
+    tod = buf[offset:].view(sc.n_pix, sc.K, T)
+    tod.copy_(base.view(sc.n_pix, sc.K, T).to("cuda"))
+    g.simulate_tod(ctx, [run.pink_job(tod, accumulate=True)])
+    torch.cuda.synchronize()
+    expect = base.view(sc.n_pix, sc.K, T) + written.cpu()
+    assert torch.equal(tod.cpu(), expect)
+
+
 @pytest.mark.parametrize("T,K", [(2**21 + 5, 2), (2**25 - 3, 1)])
 def test_pink_long_series(ctx, T, K):
     """Long series: four-step splits with 512 and with 4096 columns (the
