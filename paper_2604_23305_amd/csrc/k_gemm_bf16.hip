@@ -14,12 +14,15 @@
 // dP is split once per workgroup, when a chunk is staged into LDS; the
 // response halves come pre-split from the spectral setup.
 // Workgroup: 128 samples x 64 channels, 4 waves along time, each 32
-// samples x both 32-channel tiles (96 accumulator registers, 232 VGPRs in
+// samples x both 32-channel tiles (96 accumulator registers, 234 VGPRs in
 // all), so two workgroups share a CU and hide each other's barriers and
-// epilogues.  The 13 LDS reads of an MFMA step are issued before its 14
-// MFMAs; the loop is instantiated for one and for two live channel tiles
-// so that no branch separates them.  LDS rows are unpadded 64-byte rows
-// with an XOR swizzle of their 16-byte chunks (44 KB per workgroup).
+// epilogues.  Each wave stages its own 32 panel rows, so that part of LDS
+// needs no barrier; the response tile, shared by the four waves, is double
+// buffered, which leaves one barrier per chunk.  The 13 LDS reads of an
+// MFMA step are issued before its 14 MFMAs; the loop is instantiated for
+// one and for two live channel tiles so that no branch separates them.
+// LDS rows are unpadded 64-byte rows with an XOR swizzle of their 16-byte
+// chunks (64 KB per workgroup).
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -55,12 +58,15 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
   const int64_t row0 = (int64_t)tt * MT;
   const int ch0 = cg * NT;
 
-  // sD: [3][MT][KC] dP hi, dP lo, (dP^2) hi; sB: [5][NT][KC] B0h B0l B1h B1l B2h
-  constexpr int kStage = (3 * MT * KC + 5 * NT * KC) / 2;
+  // sD: [3][MT][KC] dP hi, dP lo, (dP^2) hi, each wave's 32 rows written
+  // and read by that wave only; sB: two buffers of [5][NT][KC] B0h B0l B1h
+  // B1l B2h, shared by the four waves
+  constexpr int kBBuf = 5 * NT * KC;   // bf16 per response buffer
+  constexpr int kStage = (3 * MT * KC + 2 * kBBuf) / 2;
   constexpr int kSmem = kStage > 4 * kEpiWaveFloats ? kStage : 4 * kEpiWaveFloats;
   __shared__ float smem[kSmem];
   __bf16* sD = reinterpret_cast<__bf16*>(smem);
-  __bf16* sB = sD + 3 * MT * KC;
+  __bf16* sB0 = sD + 3 * MT * KC;
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
@@ -77,15 +83,16 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
 
   const int64_t Fp = a.Fp;
   const int64_t KF = (int64_t)a.Kp * Fp;
-  // panel chunk: 128 rows x 32 floats = 1024 float4, 4 per thread;
-  // response chunk: 5 x 64 x 32 bf16 = 1280 x 16 bytes, 5 per thread
+  // panel chunk: each wave loads its own 32 rows x 32 floats = 256 float4,
+  // 4 per lane; response chunk: 5 x 64 x 32 bf16 = 1280 x 16 bytes, 5 per
+  // thread
   float4 rd0, rd1, rd2, rd3;
   uint4 rb0, rb1, rb2, rb3, rb4;
 #define GTOD_LD_D(q, dst, k0n)                                               \
   {                                                                          \
-    const int idx = tid + (q) * 256;                                         \
+    const int idx = lane + (q) * 64;                                         \
     dst = *reinterpret_cast<const float4*>(                                  \
-        a.panel + (row0 + (idx >> 3)) * Fp + (k0n) + 4 * (idx & 7));         \
+        a.panel + (row0 + wave * 32 + (idx >> 3)) * Fp + (k0n) + 4 * (idx & 7)); \
   }
 #define GTOD_LD_B(q, dst, k0n)                                               \
   {                                                                          \
@@ -101,7 +108,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
 // split dP into hi, lo and (dP^2) hi while staging it into LDS
 #define GTOD_ST_D(q, src)                                                    \
   {                                                                          \
-    const int idx = tid + (q) * 256;                                         \
+    const int idx = wave * 256 + lane + (q) * 64;                            \
     const float x_[4] = {src.x, src.y, src.z, src.w};                        \
     bf16x4 hi_, lo_, sq_;                                                    \
     _Pragma("unroll") for (int e = 0; e < 4; ++e) {                         \
@@ -120,7 +127,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
     const int idx = tid + (q) * 256;                                         \
     const int mm = idx >> 8, rem = idx & 255;                                \
     const int rb_ = rem >> 2;                                                \
-    *reinterpret_cast<uint4*>(&sB[(mm * NT + rb_) * KC + 8 * ((rem & 3) ^ swz(rb_))]) = src; \
+    *reinterpret_cast<uint4*>(&sBw[(mm * NT + rb_) * KC + 8 * ((rem & 3) ^ swz(rb_))]) = src; \
   }
 #define GTOD_LOAD_CHUNK(k0n)                                                 \
   GTOD_LD_D(0, rd0, k0n) GTOD_LD_D(1, rd1, k0n) GTOD_LD_D(2, rd2, k0n)       \
@@ -138,14 +145,19 @@ __global__ __launch_bounds__(256, 2) void k_gemm_bf16(GemmArgs a) {
 
   GTOD_LOAD_CHUNK(0)
   // NI live 32-channel tiles (uniform over the workgroup): the LDS reads
-  // of an MFMA step are all issued before its MFMAs
+  // of an MFMA step are all issued before its MFMAs.  One barrier per
+  // chunk: a wave's dP rows are its own (its earlier reads of them have
+  // completed before its MFMAs used them), and the response buffer a chunk
+  // fills was last read two chunks before, ahead of the previous barrier.
   auto run = [&](auto ni_c) {
     constexpr int NI = decltype(ni_c)::value;
-    for (int k0 = 0; k0 < a.Fp; k0 += KC) {
-      __syncthreads();
+    int buf = 0;
+    for (int k0 = 0; k0 < a.Fp; k0 += KC, buf ^= 1) {
+      __bf16* sBw = sB0 + buf * kBBuf;
       GTOD_STORE_CHUNK
       __syncthreads();
       if (k0 + KC < a.Fp) { GTOD_LOAD_CHUNK(k0 + KC) }
+      const __bf16* sB = sBw;
 #pragma unroll
       for (int s = 0; s < KC / 16; ++s) {
         const int rd = wave * 32 + c;
