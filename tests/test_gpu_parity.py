@@ -107,6 +107,34 @@ def test_large_source_grid_coarse_buckets(ctx):
     _compare(sc, out, ref)
 
 
+def test_sorted_panel_with_zero_cube_matches_no_cube(ctx):
+    """With an all-zero source cube the rows take the bucketed panel (row
+    records in scalar registers, neighbour reuse of table rows) and add a
+    zero source term; without a cube they take the unsorted panel.  Both
+    compute the same powers, so P_KID and sigma agree to FP32 rounding (the
+    two kernels may contract their products differently); a row or bin
+    mix-up in either would show at the level of the PWV variation."""
+    from workloads.scenario import Source
+    sc0 = tiny_scenario(F=24, K=5, P=7, T=3000)
+    sc1 = tiny_scenario(F=24, K=5, P=7, T=3000)
+    cube, gr = gen.source_cube(sc1.spectral.nu_hz, 300, 60 * gen.ARCSEC, 0.0,
+                               np.pi / 3,
+                               [dict(flux_jy=np.full(24, 5.0),
+                                     fwhm_rad=10 * gen.ARCSEC)],
+                               np.pi * 25)
+    sc1.source = Source(cube=np.zeros_like(cube), az0=gr["az0"], daz=gr["daz"],
+                        el0=gr["el0"], del_=gr["del_"])
+    sc0.source = None
+    _, out0 = run_signal(ctx, sc0, photon_noise=False)
+    _, out1 = run_signal(ctx, sc1, photon_noise=False)
+    for name in ("p_kid", "sigma"):
+        a = getattr(out0, name).cpu().numpy().astype(np.float64)
+        b = getattr(out1, name).cpu().numpy().astype(np.float64)
+        err = np.abs(a - b).max() / np.abs(a).max()
+        print(f"  {name}: max rel diff {err:.2e}", flush=True)
+        assert err <= 1e-6, (name, err)
+
+
 def test_window_of_rows_only(ctx):
     """t_begin/t_end select rows; the rest of tod stays untouched."""
     sc = configs.c1()
