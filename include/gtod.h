@@ -230,8 +230,11 @@ gtod_status gtod_load_filters(gtod_ctx* ctx, const gtod_spectral_desc* desc,
  * Noise: seed keys Philox4x32-10 with key (seed mod 2^32, seed >> 32);
  *   white noise of sample (t, k, p) uses counter (t, k, p, 0), bin j of
  *   the 1/f spectrum of series (p, k) uses counter (j, k, p, 1).
- *   PINK: PSD A_k f^-alpha_k with A_k = NEP^2_ref,k * pink_knee_hz^alpha_k
- *   (pink_alpha host [K]); t_total <= 2^25 for PINK jobs.
+ *   PINK: one-sided PSD A_k f^-alpha_k in W^2/Hz (section 2.6), with
+ *   pink_alpha host [K]; the levels are pink_A host [K] (A_k >= 0, finite)
+ *   when it is non-NULL, else A_k = NEP^2_ref,k * pink_knee_hz^alpha_k (the
+ *   1/f PSD meets the white photon-noise PSD of the reference spectrum at
+ *   the knee).  t_total <= 2^25 for PINK jobs.
  * Outputs (device, caller-owned; layout [n_pix][K][out_ld], time fastest,
  *   holding samples [out_t0, out_t0 + out_ld); out_ld = 0 means out_t0 = 0
  *   and out_ld = t_total):
@@ -263,7 +266,8 @@ typedef struct gtod_job {
   uint32_t flags;
   int32_t pix0;               /* noise-key index of pixel 0 (default 0)   */
   const double* pink_alpha;
-  double pink_knee_hz;
+  double pink_knee_hz;        /* used when pink_A is NULL                 */
+  const double* pink_A;       /* host [K] 1/f levels (W^2/Hz) or NULL     */
   int64_t out_t0, out_ld;
   float* tod;
   float* p_kid;

@@ -9,8 +9,9 @@ Readings where the paper is silent:
     z from the pink-noise Philox stream and c_j^2 = S(f_j) N f_s / 4, so
     that the expected periodogram (2 / (N f_s)) |X_j|^2 equals S(f_j);
   * x = the inverse real DFT of X including its 1/N factor;
-  * A_k = NEP^2_ref,k * f_knee^alpha_k, i.e. the 1/f PSD equals the white
-    photon-noise PSD of the reference spectrum at the knee frequency.
+  * A_k, when not given per channel, is NEP^2_ref,k * f_knee^alpha_k, i.e.
+    the 1/f PSD equals the white photon-noise PSD of the reference spectrum
+    at the knee frequency.
 
 Oracle -- test infrastructure only.
 """
@@ -28,7 +29,12 @@ def fft_length(t_total: int) -> int:
     return n
 
 
-def amplitude(nep2_ref, alpha, knee_hz):
+def amplitude(nep2_ref, alpha, knee_hz, A=None):
+    """Per-channel 1/f levels A_k of S = A_k f^-alpha_k (section 2.6).  The
+    paper leaves A a free level per channel: explicit levels A are used as
+    given; without them the knee reading above applies."""
+    if A is not None:
+        return np.asarray(A, dtype=np.float64)
     return np.asarray(nep2_ref) * knee_hz ** np.asarray(alpha)
 
 

@@ -87,6 +87,7 @@ class Job(C.Structure):
                 ("t_total", C.c_int64), ("seed", C.c_uint64),
                 ("flags", C.c_uint32), ("pix0", C.c_int32),
                 ("pink_alpha", C.c_void_p), ("pink_knee_hz", C.c_double),
+                ("pink_A", C.c_void_p),
                 ("out_t0", C.c_int64), ("out_ld", C.c_int64),
                 ("tod", C.c_void_p), ("p_kid", C.c_void_p),
                 ("sigma", C.c_void_p), ("pwv", C.c_void_p)]

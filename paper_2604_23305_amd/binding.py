@@ -344,6 +344,8 @@ class ScenarioRun:
         self.dphi = _f64(sc.dphi)
         self.dtheta = _f64(sc.dtheta)
         self.alpha = (None if sc.pink_alpha is None else _f64(sc.pink_alpha))
+        self.pink_A = (None if getattr(sc, "pink_A", None) is None
+                       else _f64(sc.pink_A))
 
     def alloc(self, with_p_kid=False, with_sigma=False, with_pwv=False,
               device="cuda", t0=0, length=None):
@@ -438,4 +440,7 @@ class ScenarioRun:
                         flags=(JOB_ACCUMULATE if accumulate else 0)
                         | (JOB_KELVIN if kelvin else 0),
                         pink_alpha=self.alpha.ctypes.data,
-                        pink_knee_hz=sc.pink_knee_hz, tod=tod.data_ptr())
+                        pink_knee_hz=sc.pink_knee_hz,
+                        pink_A=(self.pink_A.ctypes.data
+                                if self.pink_A is not None else None),
+                        tod=tod.data_ptr())

@@ -282,12 +282,17 @@ gtod_status validate(gtod_ctx* c, const gtod_job& j, int idx, JobPlan* pl) {
     // the two-pass transform holds up to 4096 x 4096 complex points
     if (j.t_total > ((int64_t)1 << 25))
       return fail(c, GTOD_EINVAL, at + "PINK series longer than 2^25 samples");
-    if (!finite_pos(j.pink_knee_hz)) return fail(c, GTOD_EINVAL, at + "pink_knee_hz must be > 0");
+    if (!j.pink_A && !finite_pos(j.pink_knee_hz))
+      return fail(c, GTOD_EINVAL, at + "pink_knee_hz must be > 0");
     if ((int64_t)j.n_pix * pl->spec->K > ((int64_t)1 << 31))
       return fail(c, GTOD_EINVAL, at + "too many series");
     for (int k = 0; k < pl->spec->K; ++k)
       if (!std::isfinite(j.pink_alpha[k]))
         return fail(c, GTOD_EINVAL, at + "pink_alpha not finite");
+    if (j.pink_A)
+      for (int k = 0; k < pl->spec->K; ++k)
+        if (!(std::isfinite(j.pink_A[k]) && j.pink_A[k] >= 0.0))
+          return fail(c, GTOD_EINVAL, at + "pink_A must be finite and >= 0");
     return GTOD_OK;
   }
   auto sc = c->screens.find(j.screen_id);
@@ -750,7 +755,8 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
       float* alpha = (float*)(hs + plan[i].off_alpha);
       const bool kel = (j.flags & GTOD_JOB_KELVIN) != 0;
       for (int k = 0; k < f.K; ++k) {
-        const double A = f.nep2ref[k] * std::pow(j.pink_knee_hz, j.pink_alpha[k]);
+        const double A = j.pink_A ? j.pink_A[k]
+                                  : f.nep2ref[k] * std::pow(j.pink_knee_hz, j.pink_alpha[k]);
         double sc = std::sqrt(A * (double)N * c->fs / 4.0) / (double)N;
         if (kel) sc *= f.kel_ib_h[k];
         scale[k] = (float)sc;

@@ -60,6 +60,7 @@ class Request:
     cube_grid: tuple = (0, 0, 0, 0.0, 0.0, 0.0, 0.0)  # n_az, n_el, ld, az0, daz, el0, del
     pink_alpha: Optional[np.ndarray] = None
     pink_knee_hz: float = 1.0
+    pink_A: Optional[np.ndarray] = None   # [K] levels; None = knee-derived
     photon_noise: bool = True
     precision: int = -1
     # filled by the engine
@@ -105,6 +106,7 @@ class Request:
                        phi0=sc.scan.phi0, theta0=sc.scan.theta0,
                        cube=run.cube, cube_grid=cube_grid,
                        pink_alpha=run.alpha, pink_knee_hz=sc.pink_knee_hz,
+                       pink_A=getattr(run, "pink_A", None),
                        photon_noise=sc.photon_noise, precision=precision)
 
 
@@ -186,7 +188,10 @@ class Engine:
         return _abi.Job(kind=_abi.JOB_PINK, spec_id=r.spec_id, n_pix=r.n_pix,
                         t_total=r.t_total, seed=r.seed, flags=0,
                         pink_alpha=r.pink_alpha.ctypes.data,
-                        pink_knee_hz=r.pink_knee_hz, tod=r.tod.data_ptr())
+                        pink_knee_hz=r.pink_knee_hz,
+                        pink_A=(r.pink_A.ctypes.data
+                                if r.pink_A is not None else None),
+                        tod=r.tod.data_ptr())
 
     def _now(self) -> float:
         return time.perf_counter() - self._t0_wall

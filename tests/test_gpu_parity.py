@@ -195,6 +195,40 @@ def test_pink_series_match_oracle(ctx):
         assert err <= TOL_PINK
 
 
+@pytest.mark.parametrize("T", [4097, 9000])
+def test_pink_explicit_levels_per_channel(ctx, T):
+    """Independent per-channel levels A_k and slopes alpha_k (section 2.6:
+    A is a free level per channel), unrelated to the knee; a zero level
+    gives a zero series."""
+    sc = tiny_scenario(F=16, K=4, P=2, T=T)
+    sc.pink_alpha = np.array([1.0, 0.5, 2.0, 1.3])
+    sc.pink_A = np.array([3.0e-34, 1.0e-33, 4.0e-35, 0.0])
+    sc.pink_knee_hz = 0.0   # unused when the levels are explicit
+    run = g.ScenarioRun(ctx, sc)
+    tod = torch.full((sc.n_pix, sc.K, T), 7.0, device="cuda")
+    g.simulate_tod(ctx, [run.pink_job(tod, accumulate=False)])
+    torch.cuda.synchronize()
+    got = tod.cpu().numpy()
+    A = opk.amplitude(None, sc.pink_alpha, None, A=sc.pink_A)
+    for p in range(2):
+        for k in range(3):
+            ref = opk.series(sc.seed, p, k, A[k], sc.pink_alpha[k], T, 160.0)
+            err = np.abs(got[p, k] - ref).max() / ref.std()
+            print(f"  pink A p{p} k{k}: max err / rms {err:.3e}", flush=True)
+            assert err <= TOL_PINK
+        assert np.all(got[p, 3] == 0.0)
+
+
+def test_pink_explicit_levels_validated(ctx):
+    sc = tiny_scenario(F=16, K=3, P=1, T=64)
+    sc.pink_alpha = np.ones(3)
+    sc.pink_A = np.array([1e-34, -1e-34, 1e-34])
+    run = g.ScenarioRun(ctx, sc)
+    tod = torch.zeros((sc.n_pix, sc.K, 64), device="cuda")
+    with pytest.raises(g.GtodError):
+        g.simulate_tod(ctx, [run.pink_job(tod, accumulate=False)])
+
+
 @pytest.mark.parametrize("T", [1, 2, 3, 100, 4097, 9000])
 def test_pink_lengths(ctx, T):
     """Lengths around powers of two, down to a single sample; includes the

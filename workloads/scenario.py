@@ -141,6 +141,8 @@ class Scenario:
     photon_noise: bool = True
     pink_alpha: Optional[np.ndarray] = None   # [K]; None = no pink noise
     pink_knee_hz: float = 1.0
+    # explicit per-channel 1/f levels A_k (W^2/Hz); None = knee-derived
+    pink_A: Optional[np.ndarray] = None
 
     @property
     def n_pix(self) -> int:
