@@ -290,6 +290,39 @@ gtod_status gtod_simulate_tod(gtod_ctx* ctx, const gtod_job* jobs,
                               int32_t n_jobs, void* hip_stream);
 
 /*
+ * gtod_simulate_tod_noalloc -- gtod_simulate_tod for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  It allocates nothing (no
+ * hipMalloc, hipFree, hipHostMalloc or allocating library routine); the
+ * caller still passes inputs and outputs, as for gtod_simulate_tod.
+ *
+ * Jobs, validation, ordering and results are those of gtod_simulate_tod:
+ * the outputs are bit-identical, since no result depends on how rows or
+ * series are chunked.  The device scratch (panel, row order, 1/f transform
+ * scratch and the staged job parameters) is a static array of
+ * GTOD_NOALLOC_SCRATCH_BYTES that the library holds on each GPU it runs
+ * on, from its first use there until the process ends, outside every
+ * context's HBM budget.  The pinned host staging and its events are made
+ * by gtod_sim_init.
+ *
+ * Sharing: every call on one GPU -- from any context, stream or host
+ * thread -- uses that GPU's one array, and it keeps the last call's
+ * contents.  Calls on one stream run in order; calls that overlap on one
+ * GPU (other streams, other host threads) race and their outputs are
+ * undefined.
+ *
+ * Limits: a SIGNAL job needs at least 128 rows of 4 F_pad + 56 bytes
+ * (F_pad = F rounded up to 32), and a PINK job of t_total samples needs
+ * 4 N bytes per series plus 64 KiB (N = the power of two >= t_total);
+ * both must fit in GTOD_NOALLOC_SCRATCH_BYTES - 8 MiB.  Larger jobs are
+ * rejected with EINVAL before anything is enqueued.
+ * Errors: those of gtod_simulate_tod, except EBUDGET.
+ */
+#define GTOD_NOALLOC_SCRATCH_BYTES (256ull << 20)
+gtod_status gtod_simulate_tod_noalloc(gtod_ctx* ctx, const gtod_job* jobs,
+                                      int32_t n_jobs, void* hip_stream);
+
+/*
  * gtod_skydip -- brightness-temperature scale of a spectral setup by a
  * simulated skydip (section 2.7): the sky brightness is varied through the
  * zenith PWV while the detected power is recorded, and a linear map between

@@ -134,16 +134,25 @@ def load_filters(ctx, nu_hz, w_hz, eta_z, pwv0_mm, dpwv_mm, t_atm_K, stages,
     return sid.value
 
 
-def simulate_tod(ctx, jobs: Sequence[_abi.Job], stream=None):
-    """Enqueue jobs on a torch stream (default: the current stream)."""
-    lib = _abi.load()
+def _enqueue(fn, ctx, jobs, stream):
     if stream is None:
         import torch
         stream = torch.cuda.current_stream()
     handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
     n = len(jobs)
     arr = (_abi.Job * max(n, 1))(*jobs)
-    _check(ctx, lib.gtod_simulate_tod(ctx, arr, n, C.c_void_p(handle)))
+    _check(ctx, fn(ctx, arr, n, C.c_void_p(handle)))
+
+
+def simulate_tod(ctx, jobs: Sequence[_abi.Job], stream=None):
+    """Enqueue jobs on a torch stream (default: the current stream)."""
+    _enqueue(_abi.load().gtod_simulate_tod, ctx, jobs, stream)
+
+
+def simulate_tod_noalloc(ctx, jobs: Sequence[_abi.Job], stream=None):
+    """As simulate_tod, in the library's static per-GPU scratch: the call
+    allocates no device memory (gtod_simulate_tod_noalloc)."""
+    _enqueue(_abi.load().gtod_simulate_tod_noalloc, ctx, jobs, stream)
 
 
 def free(ctx, kind=OBJ_CTX, obj_id=0):

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -59,6 +60,32 @@ struct SpecObj {
 constexpr int kSlots = 8;
 constexpr size_t kSlotBytes = 1 << 20;
 
+// Device scratch of gtod_simulate_tod_noalloc: one copy per GPU, resident
+// from the library's first use on that device until the process ends.  In
+// host code this name is only a stand-in for the symbol; the device
+// address comes from hipGetSymbolAddress (scratch_address below).
+static __device__ __align__(256) unsigned char scratch[GTOD_NOALLOC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;   // device -> address of its scratch
+
+// Address of `scratch` on `dev`, which must be the current device; looked
+// up once per device.
+hipError_t scratch_address(int dev, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(dev);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return hipSuccess;
+  }
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_ptr[dev] = p;
+  *out = p;
+  return hipSuccess;
+}
+
 struct StreamWs {
   hipStream_t stream = nullptr;
   float* panel = nullptr;
@@ -86,6 +113,9 @@ struct gtod_ctx {
   int32_t next_id = 1;
   std::map<void*, size_t> sizes;
   std::map<hipStream_t, StreamWs> ws;
+  // gtod_simulate_tod_noalloc: device areas inside the per-GPU scratch,
+  // pinned staging and events made at init
+  StreamWs na;
   unsigned long long* counters = nullptr;
   hipStream_t sink_streams[2] = {nullptr, nullptr};  // out-of-core runs
   std::string err;
@@ -156,6 +186,13 @@ void free_ws(gtod_ctx* c, StreamWs& w) {
   w = StreamWs{};
 }
 
+// Byte sizes of a stream workspace's panel and 1/f areas.
+void ws_sizes(const gtod_ctx* c, size_t* panel_bytes, size_t* pink_bytes) {
+  *panel_bytes = round_up((int64_t)(c->ws_bytes * 3 / 4), 256);
+  *pink_bytes = std::max<int64_t>(round_up((int64_t)(c->ws_bytes - *panel_bytes), 256),
+                                  2 * kPinkTableFloat2 * (int64_t)sizeof(float2));
+}
+
 gtod_status get_ws(gtod_ctx* c, hipStream_t s, StreamWs** out) {
   auto it = c->ws.find(s);
   if (it != c->ws.end()) {
@@ -164,9 +201,7 @@ gtod_status get_ws(gtod_ctx* c, hipStream_t s, StreamWs** out) {
   }
   StreamWs w;
   w.stream = s;
-  w.panel_bytes = round_up((int64_t)(c->ws_bytes * 3 / 4), 256);
-  w.pink_bytes = std::max<int64_t>(round_up((int64_t)(c->ws_bytes - w.panel_bytes), 256),
-                                  2 * kPinkTableFloat2 * (int64_t)sizeof(float2));
+  ws_sizes(c, &w.panel_bytes, &w.pink_bytes);
   gtod_status st;
   if ((st = dev_alloc(c, (void**)&w.panel, w.panel_bytes)) != GTOD_OK ||
       (st = dev_alloc(c, (void**)&w.pink, w.pink_bytes)) != GTOD_OK ||
@@ -190,6 +225,52 @@ gtod_status get_ws(gtod_ctx* c, hipStream_t s, StreamWs** out) {
   auto res = c->ws.emplace(s, w);
   *out = &res.first->second;
   return GTOD_OK;
+}
+
+static_assert(GTOD_NOALLOC_SCRATCH_BYTES % 256 == 0 &&
+                  GTOD_NOALLOC_SCRATCH_BYTES >= 2 * kSlots * kSlotBytes,
+              "no-alloc scratch too small for the staging slots");
+
+// Workspace of gtod_simulate_tod_noalloc, set up once by gtod_sim_init:
+// the device staging slots at the head of the GPU's scratch, then one
+// area that the panel (SIGNAL jobs) and the 1/f transform scratch (PINK
+// jobs) share -- the jobs of a call run one after another on one stream,
+// and every kernel writes what it later reads.  The pinned host slots and
+// their events are made here, so the call itself allocates nothing.
+gtod_status init_noalloc(gtod_ctx* c) {
+  void* base = nullptr;
+  const hipError_t e = scratch_address(c->device, &base);
+  if (e != hipSuccess)
+    return fail(c, GTOD_EDEVICE,
+                std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  StreamWs& w = c->na;
+  w.d_stage = static_cast<char*>(base);
+  w.panel = reinterpret_cast<float*>(static_cast<char*>(base) + kSlots * kSlotBytes);
+  w.panel_bytes = GTOD_NOALLOC_SCRATCH_BYTES - kSlots * kSlotBytes;
+  w.pink = reinterpret_cast<float2*>(w.panel);
+  w.pink_bytes = w.panel_bytes;
+  if (hipHostMalloc((void**)&w.h_stage, kSlots * kSlotBytes, hipHostMallocDefault) !=
+      hipSuccess) {
+    (void)hipGetLastError();
+    w.h_stage = nullptr;
+    return fail(c, GTOD_ENOMEM, "pinned staging allocation failed");
+  }
+  for (int i = 0; i < kSlots; ++i) {
+    if (hipEventCreateWithFlags(&w.ev[i], hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      w.ev[i] = nullptr;
+      return fail(c, GTOD_EDEVICE, "event creation failed");
+    }
+  }
+  return GTOD_OK;
+}
+
+// Releases what init_noalloc made (the device scratch itself stays).
+void free_noalloc(StreamWs& w) {
+  if (w.h_stage) (void)hipHostFree(w.h_stage);
+  for (int i = 0; i < kSlots; ++i)
+    if (w.ev[i]) (void)hipEventDestroy(w.ev[i]);
+  w = StreamWs{};
 }
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
@@ -246,7 +327,73 @@ struct JobPlan {
   const SpecObj* spec;
   int precision;
   size_t off_dphi, off_dtheta, off_scale, off_alpha;
+  // SIGNAL: cube-cell buckets, rows per chunk, pixels and samples per chunk
+  int n_buckets, cell_shift, n_az_c, pg;
+  int64_t rows_cap, Tc_max;
+  // PINK: series per batch
+  int64_t pink_per;
 };
+
+// Chunking of a validated job in areas of the given sizes: how many rows
+// (SIGNAL) or series (PINK) one launch takes.  EINVAL when not even the
+// smallest unit fits, before anything is enqueued.
+gtod_status plan_chunks(gtod_ctx* c, JobPlan* pl, int idx, size_t panel_bytes,
+                        size_t pink_bytes, const char* ws_name) {
+  const gtod_job& j = *pl->j;
+  const SpecObj& f = *pl->spec;
+  const std::string at = "job " + std::to_string(idx) + ": ";
+  if (j.kind == GTOD_JOB_PINK) {
+    int64_t N = 2;
+    while (N < j.t_total) N *= 2;
+    const int64_t M = N / 2;
+    const size_t scratch_bytes = pink_bytes - kPinkTableFloat2 * sizeof(float2);
+    const int64_t S = (int64_t)j.n_pix * f.K;
+    // a single-pass transform (M <= 2048) needs no scratch
+    int64_t per = M > (1 << kPinkLgM2) ? (int64_t)(scratch_bytes / ((size_t)M * sizeof(float2))) : S;
+    per = std::min<int64_t>(std::min<int64_t>(per, S), 65535);
+    if (per < 1) return fail(c, GTOD_EINVAL, at + "1/f series too long for " + ws_name);
+    pl->pink_per = per;
+    return GTOD_OK;
+  }
+  // with a source cube the rows are bucketed by coarse cube cell (at most
+  // kPanelMaxBuckets cells); each row then also needs a record, a key and
+  // an order slot beside its panel row
+  int n_buckets = 1, cell_shift = 0, n_az_c = 0;
+  if (j.cube) {
+    for (;; ++cell_shift) {
+      const int64_t ne = ((int64_t)j.n_el + (1 << cell_shift) - 1) >> cell_shift;
+      const int64_t na = ((int64_t)j.n_az + (1 << cell_shift) - 1) >> cell_shift;
+      if (ne * na <= kPanelMaxBuckets) {
+        n_buckets = (int)(ne * na) + 1;
+        n_az_c = (int)na;
+        break;
+      }
+    }
+  }
+  const int64_t per_row = (int64_t)f.Fp * 4 + (n_buckets > 1 ? kPanelRowInfoBytes + 8 : 0);
+  const int64_t hist_bytes = round_up((int64_t)n_buckets * 4, 256);
+  const int64_t rows_cap = std::max<int64_t>(
+      0, ((int64_t)panel_bytes - hist_bytes - 4 * 256) / per_row);
+  int pg;          // pixels per chunk
+  int64_t Tc_max;  // samples per chunk
+  if ((int64_t)j.n_pix * kRowPad <= rows_cap) {
+    pg = j.n_pix;
+    Tc_max = std::max<int64_t>(kRowPad, rows_cap / j.n_pix / kRowPad * kRowPad);
+  } else {
+    pg = (int)std::max<int64_t>(1, rows_cap / kRowPad);
+    Tc_max = kRowPad;
+  }
+  if ((int64_t)pg * kRowPad > rows_cap)
+    return fail(c, GTOD_EINVAL, at + "frequency axis too long for " + ws_name);
+  Tc_max = std::min<int64_t>(Tc_max, round_up(std::max<int64_t>(j.t_end - j.t_begin, 1), kRowPad));
+  pl->n_buckets = n_buckets;
+  pl->cell_shift = cell_shift;
+  pl->n_az_c = n_az_c;
+  pl->rows_cap = rows_cap;
+  pl->pg = pg;
+  pl->Tc_max = Tc_max;
+  return GTOD_OK;
+}
 
 gtod_status validate(gtod_ctx* c, const gtod_job& j, int idx, JobPlan* pl) {
   const std::string at = "job " + std::to_string(idx) + ": ";
@@ -417,6 +564,14 @@ gtod_status gtod_sim_init(const gtod_init_desc* d, gtod_ctx** out) {
     dev_free(c, c->counters);
     delete c;
     return fail(nullptr, GTOD_EDEVICE, "hipMemset failed");
+  }
+  st = init_noalloc(c);
+  if (st != GTOD_OK) {
+    g_init_err = c->err;
+    free_noalloc(c->na);
+    dev_free(c, c->counters);
+    delete c;
+    return st;
   }
   *out = c;
   return GTOD_OK;
@@ -705,16 +860,25 @@ gtod_status gtod_load_filters(gtod_ctx* c, const gtod_spectral_desc* d, int32_t*
   return GTOD_OK;
 }
 
-gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
-                              void* hip_stream) {
+// Body of gtod_simulate_tod and gtod_simulate_tod_noalloc: the second
+// runs in the GPU's static scratch instead of the stream's workspace.
+static gtod_status simulate(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
+                            void* hip_stream, bool noalloc) {
   if (!c) return GTOD_EINVAL;
   if (n_jobs < 0 || (n_jobs > 0 && !jobs)) return fail(c, GTOD_EINVAL, "bad job array");
   if (n_jobs == 0) return GTOD_OK;
+  // the areas the jobs run in: the stream's workspace (made on its first
+  // use, with these sizes) or the GPU's static scratch
+  size_t panel_bytes = c->na.panel_bytes, pink_bytes = c->na.pink_bytes;
+  if (!noalloc) ws_sizes(c, &panel_bytes, &pink_bytes);
+  const char* ws_name = noalloc ? "the no-alloc scratch" : "the workspace";
   std::vector<JobPlan> plan(n_jobs);
   size_t stage_bytes = 0;
   for (int i = 0; i < n_jobs; ++i) {
+    plan[i] = JobPlan{};
     plan[i].j = &jobs[i];
     gtod_status st = validate(c, jobs[i], i, &plan[i]);
+    if (st == GTOD_OK) st = plan_chunks(c, &plan[i], i, panel_bytes, pink_bytes, ws_name);
     if (st != GTOD_OK) return st;
     const gtod_job& j = jobs[i];
     if (j.kind == GTOD_JOB_SIGNAL) {
@@ -733,9 +897,11 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
   if (stage_bytes > kSlotBytes) return fail(c, GTOD_EINVAL, "per-call job parameters exceed 1 MiB");
   HIP_TRY(c, hipSetDevice(c->device));
   hipStream_t s = (hipStream_t)hip_stream;
-  StreamWs* w = nullptr;
-  gtod_status st = get_ws(c, s, &w);
-  if (st != GTOD_OK) return st;
+  StreamWs* w = &c->na;
+  if (!noalloc) {
+    const gtod_status st = get_ws(c, s, &w);
+    if (st != GTOD_OK) return st;
+  }
 
   // stage the small per-job arrays through a pinned slot
   const int slot = w->slot;
@@ -801,11 +967,8 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
       a.tab = w->pink;
       a.tab_w = w->pink;
       a.scratch = w->pink + kPinkTableFloat2;
-      const size_t scratch_bytes = w->pink_bytes - kPinkTableFloat2 * sizeof(float2);
       const int64_t S = (int64_t)j.n_pix * f.K;
-      int64_t per = a.M1 > 1 ? (int64_t)(scratch_bytes / ((size_t)a.M * sizeof(float2))) : S;
-      per = std::min<int64_t>(std::min<int64_t>(per, S), 65535);
-      if (per < 1) return fail(c, GTOD_EINVAL, "1/f series longer than the workspace");
+      const int64_t per = plan[i].pink_per;
       launch_pink_tables(a, s);
       for (int64_t s0 = 0; s0 < S; s0 += per) {
         a.s0 = s0;
@@ -820,37 +983,9 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
     const ScreenObj& sc = *plan[i].scr;
     const int64_t T = j.t_end - j.t_begin;
     if (T == 0) continue;
-    // with a source cube the rows are bucketed by coarse cube cell (at most
-    // kPanelMaxBuckets cells); each row then also needs a record, a key and
-    // an order slot beside its panel row
-    int n_buckets = 1, cell_shift = 0, n_az_c = 0;
-    if (j.cube) {
-      for (;; ++cell_shift) {
-        const int64_t ne = ((int64_t)j.n_el + (1 << cell_shift) - 1) >> cell_shift;
-        const int64_t na = ((int64_t)j.n_az + (1 << cell_shift) - 1) >> cell_shift;
-        if (ne * na <= kPanelMaxBuckets) {
-          n_buckets = (int)(ne * na) + 1;
-          n_az_c = (int)na;
-          break;
-        }
-      }
-    }
-    const int64_t per_row = (int64_t)f.Fp * 4 + (n_buckets > 1 ? kPanelRowInfoBytes + 8 : 0);
-    const int64_t hist_bytes = round_up((int64_t)n_buckets * 4, 256);
-    const int64_t rows_cap = std::max<int64_t>(
-        0, ((int64_t)w->panel_bytes - hist_bytes - 4 * 256) / per_row);
-    int pg;          // pixels per chunk
-    int64_t Tc_max;  // samples per chunk
-    if ((int64_t)j.n_pix * kRowPad <= rows_cap) {
-      pg = j.n_pix;
-      Tc_max = std::max<int64_t>(kRowPad, rows_cap / j.n_pix / kRowPad * kRowPad);
-    } else {
-      pg = (int)std::max<int64_t>(1, rows_cap / kRowPad);
-      Tc_max = kRowPad;
-    }
-    if ((int64_t)pg * kRowPad > rows_cap)
-      return fail(c, GTOD_EINVAL, "frequency axis too long for the workspace");
-    Tc_max = std::min<int64_t>(Tc_max, round_up(T, kRowPad));
+    const int n_buckets = plan[i].n_buckets, cell_shift = plan[i].cell_shift;
+    const int n_az_c = plan[i].n_az_c, pg = plan[i].pg;
+    const int64_t rows_cap = plan[i].rows_cap, Tc_max = plan[i].Tc_max;
     PanelArgs pa{};
     pa.tau = f.tau;
     pa.E = f.E;
@@ -964,6 +1099,16 @@ gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
   HIP_TRY(c, hipEventRecord(w->ev[slot], s));
   w->ev_used[slot] = true;
   return GTOD_OK;
+}
+
+gtod_status gtod_simulate_tod(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
+                              void* hip_stream) {
+  return simulate(c, jobs, n_jobs, hip_stream, false);
+}
+
+gtod_status gtod_simulate_tod_noalloc(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
+                                      void* hip_stream) {
+  return simulate(c, jobs, n_jobs, hip_stream, true);
 }
 
 gtod_status gtod_skydip(gtod_ctx* c, int32_t spec_id, double el_rad, double pwv_lo_mm,
@@ -1402,6 +1547,7 @@ gtod_status gtod_free(gtod_ctx* c, int32_t kind, int32_t id) {
     for (auto& kv : c->screens) dev_free(c, kv.second.pwv);
     for (auto& kv : c->specs) free_spec(c, kv.second);
     for (auto& kv : c->ws) free_ws(c, kv.second);
+    free_noalloc(c->na);
     for (hipStream_t s : c->sink_streams)
       if (s) (void)hipStreamDestroy(s);
     dev_free(c, c->counters);
