@@ -76,6 +76,10 @@ def parse():
                     help="after the simulation steps, time gtod_reduce "
                          "(common-mode subtraction + 31x31 inverse-variance "
                          "maps) on the Kelvin TOD; needs --kelvin")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="with the default c3 workload, skip the c4 "
+                         "(split BF16) and c5 (serving) measurements that "
+                         "the JSON line otherwise carries beside it")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (counter "
                          "calibration for HBM byte counts)")
@@ -332,15 +336,27 @@ def d2h_gbs(torch, tod, n_bytes=1 << 30, reps=3):
     return flat.numel() * 4 / (ms / 1e3) / 1e9
 
 
-def elementwise(kern, workload, copy):
+def elementwise(kern, workload, copy, sc):
     """HBM view of the elementwise kernels (panel, 1/f passes): algorithmic
     GB/s against the 8 TB/s peak and against the measured copy bandwidth,
-    plus the measured fetch+write bytes where a profile holds them."""
+    plus the measured fetch+write bytes where a profile holds them.
+
+    The panel's algorithmic bytes are what any panel kernel must move: the
+    dP row it writes (4 F bytes) and the screen cells (32 bytes) per row,
+    plus one read of the source cube per launch.  The library's per-row
+    count (20 F + 32: four corner spectra per row) describes a kernel that
+    reads every row's corners from memory; in cube-cell order the corners
+    come mostly from the caches, so that count is not a traffic bound."""
     out = {}
     for name in ("panel", "pink_pass1", "pink_pass2"):
         if name not in kern:
             continue
         gbs = kern[name]["alg_gbs"]
+        if name == "panel":
+            k = kern[name]
+            rows = k["alg_gbs"] * 1e9 * k["avg_ms"] / 1e3 / (20.0 * sc.F + 32.0)
+            cube = 0.0 if sc.source is None else sc.source.cube.size * 4.0
+            gbs = (rows * (4.0 * sc.F + 32.0) + cube) / (k["avg_ms"] / 1e3) / 1e9
         d = {"alg_gbs": gbs, "frac_hbm_peak": gbs * 1e9 / HBM_PEAK,
              "frac_copy": gbs / copy}
         tf = os.path.join(ROOT, "profiles", f"traffic_{name}_{workload}.json")
@@ -457,6 +473,86 @@ def run_c5(args, g, torch):
     return summ, prof, rep, ("split" if prec == g.PREC_SPLIT_BF16 else "fp32")
 
 
+def measure(g, torch, ctx, jobs, stream, steps, warmup, label):
+    """Warm-up calls, then `steps` timed calls of the whole simulation, each
+    one gtod_simulate_tod call on `stream`; per-kernel times come from the
+    library's events on that stream."""
+    for w in range(warmup):
+        g.simulate_tod(ctx, jobs, stream)
+        torch.cuda.synchronize()
+        print(f"# {label}: warmup {w} done", file=sys.stderr, flush=True)
+    g.profile_enable(ctx, True)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for s in range(steps):
+        g.simulate_tod(ctx, jobs, stream)
+        ev[s + 1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = g.profile_read(ctx)
+    g.profile_enable(ctx, False)
+    step_ms = [ev[s].elapsed_time(ev[s + 1]) for s in range(steps)]
+    print(f"# {label}: timed {steps} steps in {elapsed:.3f} s",
+          file=sys.stderr, flush=True)
+    return elapsed, step_ms, kernel_table(prof)
+
+
+def latency(step_ms):
+    import numpy as np
+    return {"p50": float(np.percentile(step_ms, 50)),
+            "p99": float(np.percentile(step_ms, 99)),
+            "min": float(np.min(step_ms)), "max": float(np.max(step_ms))}
+
+
+def c4_measure(args, g, torch, ctx, run3, sc3, stream):
+    """The split-precision IFU workload on the context, screen and spectral
+    setup of the c3 run (c4 differs only by its faint extended source and
+    noise seed): the same whole-simulation steps, hi+lo BF16 contraction."""
+    from workloads import configs
+    sc = configs.c4(reuse_screen=sc3.screen)
+    run = g.ScenarioRun(ctx, sc, screen_id=run3.screen_id,
+                        spec_id=run3.spec_id)
+    out = run.alloc()
+    jobs = [run.signal_job(out, precision=g.PREC_SPLIT_BF16),
+            run.pink_job(out.tod, accumulate=True)]
+    elapsed, step_ms, kern = measure(g, torch, ctx, jobs, stream, args.steps,
+                                     args.warmup, "c4")
+    del out, run
+    value = sc.n_pix * sc.K * sc.t_total * args.steps / elapsed
+    res = {"value": value, "unit": "detector-samples/s",
+           "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": elapsed * 1e3 / args.steps, "dtype": "bf16x2",
+           "config": {"workload": f"c4: {WORKLOADS['c4']}",
+                      "pixels": sc.n_pix, "channels": sc.K,
+                      "freq_bins": sc.F, "samples": sc.t_total,
+                      "precision": "split"},
+           "latency_ms": latency(step_ms),
+           "roofline": roofline(kern, "c4"),
+           "end_to_end": end_to_end(value, sc, "split"),
+           "kernels": kern}
+    return res, sc
+
+
+def c5_measure(args, g, torch):
+    """The serving stream, summarised for the c3 line."""
+    summ, prof, rep, prec_name = run_c5(args, g, torch)
+    kern = kernel_table(prof)
+    return {"value": summ["det_samples_per_s"], "unit": "detector-samples/s",
+            "makespan_ms": summ["makespan_s"] * 1e3,
+            "requests": summ["requests"], "det_samples": summ["det_samples"],
+            "dtype": "f32" if prec_name == "fp32" else "bf16x2",
+            "config": {"workload": f"c5: {WORKLOADS['c5']}",
+                       "precision": prec_name},
+            "latency_ms": {"p50": summ["p50_ms"], "p99": summ["p99_ms"],
+                           "mean": summ["mean_ms"],
+                           "what": "scheduled arrival to the completion "
+                                   "event of the request's last job, "
+                                   "outputs in HBM"},
+            "roofline": roofline(kern, "c5"), "kernels": kern}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -540,30 +636,10 @@ def main():
     print(f"# setup {setup_s:.1f} s; workload {args.workload} ({prec_name})",
           file=sys.stderr, flush=True)
 
-    for w in range(args.warmup):
-        g.simulate_tod(ctx, jobs, stream)
-        torch.cuda.synchronize()
-        print(f"# warmup {w} done", file=sys.stderr, flush=True)
-
-    g.profile_enable(ctx, True)
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev[0].record(stream)
-    for s in range(args.steps):
-        g.simulate_tod(ctx, jobs, stream)
-        ev[s + 1].record(stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    prof = g.profile_read(ctx)
-    g.profile_enable(ctx, False)
-    step_ms = [ev[s].elapsed_time(ev[s + 1]) for s in range(args.steps)]
+    elapsed, step_ms, kern = measure(g, torch, ctx, jobs, stream, args.steps,
+                                     args.warmup, args.workload)
     det_per_step = sc.n_pix * sc.K * sc.t_total
     value = det_per_step * args.steps / elapsed
-    print(f"# timed {args.steps} steps in {elapsed:.3f} s", file=sys.stderr,
-          flush=True)
-
-    kern = kernel_table(prof)
     roof = roofline(kern, args.workload)
     red = run_reduce(args, g, torch, ctx, run, sc, out, stream) \
         if args.reduce else None
@@ -586,26 +662,36 @@ def main():
                    "samples": sc.t_total, "precision": prec_name,
                    "tod_unit": "K" if kel else "W",
                    "parallelism": "single GPU"},
-        "latency_ms": {"p50": float(np.percentile(step_ms, 50)),
-                       "p99": float(np.percentile(step_ms, 99)),
-                       "min": float(np.min(step_ms)),
-                       "max": float(np.max(step_ms))},
+        "latency_ms": latency(step_ms),
         "roofline": roof,
-        "elementwise": elementwise(kern, args.workload, copy),
+        "elementwise": elementwise(kern, args.workload, copy, sc),
         "end_to_end": end_to_end(value, sc, prec_name),
         "copy_gbs": copy,
         "d2h_gbs": d2h_gbs(torch, out.tod),
         "kernels": kern,
     }
+    extras = (args.workload == "c3" and not args.headline_only
+              and not kel and not red)
+    sc4 = None
+    if extras:
+        del out
+        res["c4"], sc4 = c4_measure(args, g, torch, ctx, run, sc, stream)
+        res["c4"]["vs_c3_fp32"] = res["c4"]["value"] / value
     g.free(ctx)
-    del out
+    if not extras:
+        del out
     torch.cuda.empty_cache()
+    if extras:
+        res["c5"] = c5_measure(args, g, torch)
+        torch.cuda.empty_cache()
     if kel:
         res["kelvin"] = kel
     if red:
         res["reduce"] = red
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(sc, args.cpu_seconds)
+        if sc4 is not None:
+            res["c4"]["cpu_baseline"] = cpu_baseline(sc4, args.cpu_seconds / 2)
         if kel:
             kel["skydip_oracle_ms"] = cpu_skydip(sc, args.kelvin) * 1e3
         if red:

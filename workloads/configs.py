@@ -140,13 +140,18 @@ def daisy_scan():
 
 
 def c3(t_total=576000, screen_shape=(1024, 262144), n_side=7, noise=True,
-       F=3000, K=347, faint=False, name="c3", seed=3):
+       F=3000, K=347, faint=False, name="c3", seed=3, reuse_screen=None):
+    """reuse_screen: a Screen made by an earlier call with the same
+    screen_shape (c3 and c4 share theirs), to skip regenerating it."""
     sp = spectral(F, lorentz_bank(K, eta_peak=0.16, mode="filterbank"),
                   cascade_c2())
     dphi, dth = gen.square_spaxels(n_side, 12 * ARCSEC)
+    if reuse_screen is not None:
+        assert reuse_screen.pwv_mm.shape == tuple(screen_shape)
     return Scenario(
         name=name, f_sample_hz=F_SAMPLE, spectral=sp,
-        screen=screen(*screen_shape, 1003),
+        screen=(reuse_screen if reuse_screen is not None
+                else screen(*screen_shape, 1003)),
         scan=daisy_scan(), dphi=dphi, dtheta=dth, t_total=t_total,
         source=line_source(sp.nu_hz, n_grid=121, half=150 * ARCSEC,
                            faint=faint),
