@@ -1,11 +1,21 @@
-"""Parity at the full workload sizes, on sampled outputs.
+"""Parity at the full workload sizes, on sampled outputs of the full runs.
 
-c3 (IFU, 49 px x 347 ch x 576000 samples) runs whole on the GPU in the
-launch configuration bench.py times (8 GiB workspace); the oracle computes
-3 pixels x 3 windows (start, middle, end of the hour) and four full 1/f
-series.  c4 (split BF16) is checked on windows, including the faint
-extended source (its signal, TOD with minus TOD without, recovered to 1%).
+c3 (IFU, 49 px x 347 ch x 576000 samples, FP32) and c4 (the same plus a
+faint extended source, split BF16 contraction) each run whole on the GPU in
+the launch configuration bench.py times: one call, 8 GiB workspace, the
+SIGNAL job over every row (here also writing P_KID and sigma) and the 1/f
+job over every series.  The oracle computes all 49 pixels x 3 windows of
+2048 samples (start, middle and end of the hour; the end window is where
+an error in the FP64 trajectory would show) and four full 1/f series.
+
+Bars, element by element: P_KID and the TOD within 1e-6 relative, sigma
+within 1e-5 relative, the 1/f series within 1e-5 of its rms.  The error
+against the oracle is printed per channel (max, p99.99 and median over the
+sampled rows) for every output.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 import torch
@@ -18,98 +28,170 @@ from workloads import configs
 
 pytestmark = pytest.mark.gpu
 
-WIN = 512
+WIN = 2048
+BARS = (("p_kid", 1e-6), ("sigma", 1e-5), ("tod", 1e-6))
 
 
 def windows(T):
     return [0, T // 2 - WIN // 2, T - WIN]
 
 
-@pytest.fixture(scope="module")
-def c3_run():
-    sc = configs.c3()
+def oracle_windows(sc, pixels, starts):
+    """Oracle outputs for every (pixel, window start), computed in threads
+    (NumPy releases the GIL in its array loops)."""
+    jobs = [(p, a) for p in pixels for a in starts]
+    n = min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(n) as ex:
+        res = list(ex.map(lambda pa: oracle.tod.simulate(
+            sc, pa[1], pa[1] + WIN, pixels=[pa[0]]), jobs))
+    return dict(zip(jobs, res))
+
+
+def per_channel_table(label, errs):
+    """errs: name -> [K][n] relative errors.  Prints one line per channel
+    and returns the worst channel's figures per output."""
+    K = next(iter(errs.values())).shape[0]
+    stats = {}
+    for name, e in errs.items():
+        stats[name] = np.stack([e.max(axis=1),
+                                np.quantile(e, 0.9999, axis=1),
+                                np.median(e, axis=1)], axis=1)
+    head = "  ".join(f"{n:>8s} max   p99.99   median" for n in errs)
+    print(f"  {label}: relative error per channel vs the FP64 oracle\n"
+          f"    k    {head}", flush=True)
+    for k in range(K):
+        row = "  ".join(" ".join(f"{v:.2e}" for v in stats[n][k])
+                        for n in errs)
+        print(f"  {k:4d}    {row}", flush=True)
+    return {n: float(s[:, 0].max()) for n, s in stats.items()}
+
+
+def check_full_run(label, sc, out):
+    """All pixels x three windows of a full run against the oracle."""
+    starts = windows(sc.t_total)
+    pixels = list(range(sc.n_pix))
+    print(f"  {label}: oracle on {len(pixels)} px x {len(starts)} windows "
+          f"of {WIN}", flush=True)
+    refs = oracle_windows(sc, pixels, starts)
+    errs = {n: np.empty((sc.K, len(pixels) * len(starts) * WIN), np.float32)
+            for n, _ in BARS}
+    worst = {n: (0.0, None) for n, _ in BARS}
+    for i, (p, a) in enumerate((p, a) for p in pixels for a in starts):
+        ref = refs[(p, a)]
+        for name, _ in BARS:
+            got = getattr(out, name)[p, :, a:a + WIN].cpu().numpy()
+            e = rel_err(got, ref[name][0])
+            errs[name][:, i * WIN:(i + 1) * WIN] = e
+            if e.max() > worst[name][0]:
+                worst[name] = (float(e.max()), (p, a))
+    for name, _ in BARS:
+        report(f"{label} {name} (worst at p, t0 = {worst[name][1]})",
+               errs[name])
+    per_channel_table(label, errs)
+    for name, tol in BARS:
+        assert worst[name][0] <= tol, (label, name, worst[name])
+
+
+def full_run(sc, precision):
     ctx = new_ctx(workspace_bytes=8 << 30)
     run = g.ScenarioRun(ctx, sc)
     out = run.alloc(with_p_kid=True, with_sigma=True)
     pink = torch.zeros_like(out.tod)
-    print(" c3: enqueue full run", flush=True)
-    g.simulate_tod(ctx, [run.signal_job(out),
+    print(f" {sc.name}: enqueue full run", flush=True)
+    g.simulate_tod(ctx, [run.signal_job(out, precision=precision),
                          run.pink_job(pink, accumulate=False)])
     torch.cuda.synchronize()
-    yield sc, ctx, run, out, pink
-    del out, pink
-    g.free(ctx)
-    torch.cuda.empty_cache()
+    return ctx, run, out, pink
 
 
-@pytest.mark.parametrize("p", [0, 24, 48])
-def test_c3_windows_match_oracle(c3_run, p):
-    sc, ctx, run, out, _ = c3_run
-    for a in windows(sc.t_total):
-        ref = oracle.tod.simulate(sc, a, a + WIN, pixels=[p])
-        for name, tol in (("p_kid", 1e-6), ("sigma", 1e-5), ("tod", 1e-6)):
-            got = getattr(out, name)[p:p + 1, :, a:a + WIN].cpu().numpy()
-            e = rel_err(got, ref[name])
-            report(f"p{p} t{a} {name}", e)
-            assert e.max() <= tol, (name, p, a)
+@pytest.fixture(scope="module")
+def c3_screen():
+    """The 1024 x 262144 screen that c3 and c4 share (host copy)."""
+    return configs.c3(t_total=WIN).screen
 
 
-def test_c3_no_clamps_and_finite(c3_run):
-    sc, ctx, run, out, pink = c3_run
-    assert g.counters(ctx) == (0, 0)
-    assert bool(torch.isfinite(out.tod).all())
-    assert bool(torch.isfinite(pink).all())
+class TestC3:
+    @pytest.fixture(scope="class")
+    def c3(self, c3_screen):
+        sc = configs.c3(reuse_screen=c3_screen)
+        ctx, run, out, pink = full_run(sc, g.PREC_FP32)
+        yield sc, ctx, run, out, pink
+        del out, pink
+        g.free(ctx)
+        torch.cuda.empty_cache()
+
+    def test_all_pixels_three_windows(self, c3):
+        sc, ctx, run, out, _ = c3
+        check_full_run("c3 FP32", sc, out)
+
+    def test_no_clamps_and_finite(self, c3):
+        sc, ctx, run, out, pink = c3
+        assert g.counters(ctx) == (0, 0)
+        assert bool(torch.isfinite(out.tod).all())
+        assert bool(torch.isfinite(pink).all())
+
+    @pytest.mark.parametrize("p,k", [(0, 0), (24, 173), (48, 346), (7, 100)])
+    def test_pink_series(self, c3, p, k):
+        sc, ctx, run, out, pink = c3
+        nep2 = oracle.tod.reference_nep2(sc)
+        A = opk.amplitude(nep2, sc.pink_alpha, sc.pink_knee_hz)
+        ref = opk.series(sc.seed, p, k, A[k], sc.pink_alpha[k], sc.t_total,
+                         sc.f_sample_hz)
+        got = pink[p, k].cpu().numpy()
+        err = np.abs(got - ref).max() / ref.std()
+        print(f"  pink p{p} k{k}: max err / rms {err:.3e}", flush=True)
+        assert err <= 1e-5
 
 
-@pytest.mark.parametrize("p,k", [(0, 0), (24, 173), (48, 346), (7, 100)])
-def test_c3_pink_series(c3_run, p, k):
-    sc, ctx, run, out, pink = c3_run
-    nep2 = oracle.tod.reference_nep2(sc)
-    A = opk.amplitude(nep2, sc.pink_alpha, sc.pink_knee_hz)
-    ref = opk.series(sc.seed, p, k, A[k], sc.pink_alpha[k], sc.t_total,
-                     sc.f_sample_hz)
-    got = pink[p, k].cpu().numpy()
-    err = np.abs(got - ref).max() / ref.std()
-    print(f"  pink p{p} k{k}: max err / rms {err:.3e}", flush=True)
-    assert err <= 1e-5
+class TestC4:
+    @pytest.fixture(scope="class")
+    def c4(self, c3_screen):
+        sc = configs.c4(reuse_screen=c3_screen)
+        ctx, run, out, pink = full_run(sc, g.PREC_SPLIT_BF16)
+        yield sc, ctx, run, out, pink
+        del out, pink
+        g.free(ctx)
+        torch.cuda.empty_cache()
 
+    def test_all_pixels_three_windows(self, c4):
+        sc, ctx, run, out, _ = c4
+        check_full_run("c4 split", sc, out)
 
-def _window_run(ctx, run, a, precision, photon):
-    out = run.alloc(with_p_kid=True, with_sigma=True, t0=a, length=WIN)
-    g.simulate_tod(ctx, [run.signal_job(out, a, a + WIN, precision=precision,
-                                        photon_noise=photon)])
-    torch.cuda.synchronize()
-    return out
+    def test_no_clamps_and_finite(self, c4):
+        sc, ctx, run, out, pink = c4
+        assert g.counters(ctx) == (0, 0)
+        assert bool(torch.isfinite(out.tod).all())
+        assert bool(torch.isfinite(pink).all())
 
-
-def test_c4_split_windows_and_faint_source():
-    sc = configs.c4()
-    sc0 = configs.c4(faint=False)
-    ctx = new_ctx(workspace_bytes=8 << 30, precision=g.PREC_SPLIT_BF16)
-    try:
-        run = g.ScenarioRun(ctx, sc)
+    def test_faint_source_survives(self, c4, c3_screen):
+        """The faint extended source (peak 1e-4 of the loading): its signal
+        per channel, P_KID with the source minus P_KID without it, summed
+        over a window, is recovered from the split-precision full run to
+        1% of the oracle's wherever the oracle's exceeds 1e-3 of its
+        largest value.  The run without the source is a window job."""
+        sc, ctx, run, out, _ = c4
+        sc0 = configs.c4(faint=False, reuse_screen=c3_screen)
         run0 = g.ScenarioRun(ctx, sc0, screen_id=run.screen_id,
                              spec_id=run.spec_id)
         pix = [24, 17]
         for a in windows(sc.t_total):
-            o1 = _window_run(ctx, run, a, g.PREC_SPLIT_BF16, True)
-            o0 = _window_run(ctx, run0, a, g.PREC_SPLIT_BF16, False)
-            r1 = oracle.tod.simulate(sc, a, a + WIN, pixels=pix)
+            o0 = run0.alloc(with_p_kid=True, t0=a, length=WIN)
+            g.simulate_tod(ctx, [run0.signal_job(
+                o0, a, a + WIN, precision=g.PREC_SPLIT_BF16,
+                photon_noise=False)])
+            torch.cuda.synchronize()
+            r1 = oracle.tod.simulate(sc, a, a + WIN, pixels=pix,
+                                     photon_noise=False)
             r0 = oracle.tod.simulate(sc0, a, a + WIN, pixels=pix,
                                      photon_noise=False)
-            for name, tol in (("p_kid", 1e-6), ("sigma", 1e-5), ("tod", 1e-6)):
-                e = rel_err(getattr(o1, name)[pix].cpu().numpy(), r1[name])
-                report(f"c4 t{a} {name}", e)
-                assert e.max() <= tol
-            d_gpu = (o1.p_kid[pix].double() - o0.p_kid[pix].double()).sum(-1)
+            p1 = out.p_kid[pix, :, a:a + WIN].double()
+            d_gpu = (p1 - o0.p_kid[pix].double()).sum(-1).cpu().numpy()
             d_ref = (r1["p_kid"] - r0["p_kid"]).sum(-1)
-            d_gpu = d_gpu.cpu().numpy()
             seen = np.abs(d_ref) > 1e-3 * np.abs(d_ref).max()
             if not seen.any():
                 continue
             frac = np.abs(d_gpu - d_ref)[seen] / np.abs(d_ref)[seen]
-            print(f"  faint source t{a}: signal/P {np.abs(d_ref).max() / r1['p_kid'].sum(-1).max():.2e}"
-                  f", worst recovery error {frac.max():.2e}", flush=True)
+            ratio = np.abs(d_ref).max() / r1["p_kid"].sum(-1).max()
+            print(f"  faint source t{a}: signal/P {ratio:.2e}, worst "
+                  f"recovery error {frac.max():.2e}", flush=True)
             assert frac.max() <= 0.01
-    finally:
-        g.free(ctx)

@@ -111,9 +111,10 @@ def test_sorted_panel_with_zero_cube_matches_no_cube(ctx):
     """With an all-zero source cube the rows take the bucketed panel (row
     records in scalar registers, neighbour reuse of table rows) and add a
     zero source term; without a cube they take the unsorted panel.  Both
-    compute the same powers, so P_KID and sigma agree to FP32 rounding (the
-    two kernels may contract their products differently); a row or bin
-    mix-up in either would show at the level of the PWV variation."""
+    compute the same powers, so P_KID and sigma agree element by element
+    to FP32 rounding (the two kernels may contract their products
+    differently); a row or bin mix-up in either, even one confined to weak
+    channels or rows, would show at the level of the PWV variation."""
     from workloads.scenario import Source
     sc0 = tiny_scenario(F=24, K=5, P=7, T=3000)
     sc1 = tiny_scenario(F=24, K=5, P=7, T=3000)
@@ -129,10 +130,49 @@ def test_sorted_panel_with_zero_cube_matches_no_cube(ctx):
     _, out1 = run_signal(ctx, sc1, photon_noise=False)
     for name in ("p_kid", "sigma"):
         a = getattr(out0, name).cpu().numpy().astype(np.float64)
-        b = getattr(out1, name).cpu().numpy().astype(np.float64)
-        err = np.abs(a - b).max() / np.abs(a).max()
-        print(f"  {name}: max rel diff {err:.2e}", flush=True)
-        assert err <= 1e-6, (name, err)
+        b = getattr(out1, name).cpu().numpy()
+        err = rel_err(b, a)
+        report(name, err)
+        assert err.max() <= 1e-6, (name, err.max())
+
+
+@pytest.mark.parametrize("prec", [g.PREC_FP32, g.PREC_SPLIT_BF16])
+def test_table_axis_clamp_matches_oracle(prec):
+    """Screen PWV that leaves the table's PWV axis at both ends (section 2.4
+    lookup table; PWV outside the axis is clamped to it, reading R6), in
+    the default (non-strict) mode: every output element against the oracle,
+    and the table-clamp counter equal to the number of rows whose PWV lies
+    outside the axis (an integer, compared exactly).  The axis is narrow,
+    0.9-1.1 mm, and the screen spans 0.77-1.26 mm, so that the spectra stay
+    within the range the reference-row contraction keeps to 1e-6 (a sky
+    far from the reference, such as a 0-3 mm sweep through opaque lines,
+    loses accuracy as c0 / P_KID grows)."""
+    import dataclasses
+    from workloads.scenario import Screen
+    sc = tiny_scenario(F=40, K=7, P=3, T=2000)
+    lines = gen.absorption_lines(3, lo_hz=300e9, hi_hz=340e9)
+    ez, p0, dp = gen.zenith_transmission_table(sc.spectral.nu_hz, lines,
+                                               0.9, 0.01, 21)
+    sc.spectral = dataclasses.replace(sc.spectral, eta_z=ez, pwv0_mm=p0,
+                                      dpwv_mm=dp)
+    sc.screen = Screen(pwv_mm=gen.pwv_screen(16, 512, 33, 1.0, 0.15),
+                       dx_m=0.5, dy_m=0.5, ix0=4.0, iy0=7.5)
+    ref = oracle.tod.simulate(sc)
+    sp = sc.spectral
+    top = sp.pwv0_mm + (sp.eta_z.shape[0] - 1) * sp.dpwv_mm
+    low = int((ref["pwv"] < sp.pwv0_mm).sum())
+    high = int((ref["pwv"] > top).sum())
+    print(f"  rows below the axis {low}, above {high}", flush=True)
+    assert low > 1000 and high > 1000
+    c = new_ctx()
+    try:
+        _, out = run_signal(c, sc, precision=prec, with_pwv=True)
+        _compare(sc, out, ref)
+        np.testing.assert_allclose(out.pwv.cpu().numpy(), ref["pwv"],
+                                   rtol=1e-7, atol=1e-9)
+        assert g.counters(c) == (int(ref["clamps"]), low + high)
+    finally:
+        g.free(c)
 
 
 def test_window_of_rows_only(ctx):
