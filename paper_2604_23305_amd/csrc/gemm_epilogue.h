@@ -3,9 +3,10 @@
 // Accumulators are in panel units (powers times 2^p); C2 holds dP^2 and
 // carries 2^2p.
 //
-// Each wave owns NI x NJ accumulator tiles of 32 channels x 32 samples (3
-// products); tile (i, j) starts at channel ch_base + 32 i and row
-// row_base + 32 j.  A tile is first written to the wave's own LDS slice
+// Each wave owns NI x NJ accumulator tiles of 32 channels x 32 samples;
+// tile (i, j) starts at channel ch_base + 32 i and row row_base + 32 j.
+// With NP = 3 the products are C0, C1 and C2 as above; with NP = 2 the
+// kernel has already added C2 2^-p into C1.  A tile is first written to the wave's own LDS slice
 // (kEpiWaveFloats floats at spk, distinct for each wave) with
 // static register indices, then read back by a compact loop in which lane
 // l handles sample (l mod 32) of channel rows 2s + l/32: stores are runs of
@@ -24,10 +25,11 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kEpiPitch = 33;
 constexpr int kEpiWaveFloats = 2 * 32 * kEpiPitch;
 
-template <int NI, int NJ>
+template <int NI, int NJ, int NP>
 __device__ __forceinline__ void contraction_epilogue(
-    const GemmArgs& a, f32x16 (&acc)[3][NI][NJ], float* spk,
+    const GemmArgs& a, f32x16 (&acc)[NP][NI][NJ], float* spk,
     int64_t row_base, int ch_base, const bool (&live)[NI]) {
+  static_assert(NP == 2 || NP == 3, "two or three products");
   const int lane = threadIdx.x & 63;
   const int h = lane >> 5, c = lane & 31;
   float* sn2 = spk + 32 * kEpiPitch;
@@ -40,7 +42,10 @@ __device__ __forceinline__ void contraction_epilogue(
       for (int e = 0; e < 16; ++e) {
         const int chl = 8 * (e >> 2) + 4 * h + (e & 3);
         spk[chl * kEpiPitch + c] = acc[0][i][j][e];
-        sn2[chl * kEpiPitch + c] = acc[1][i][j][e] + acc[2][i][j][e] * a.pinv_f;
+        if constexpr (NP == 3)
+          sn2[chl * kEpiPitch + c] = acc[1][i][j][e] + acc[NP - 1][i][j][e] * a.pinv_f;
+        else
+          sn2[chl * kEpiPitch + c] = acc[1][i][j][e];
       }
       __syncthreads();
       if (!live[i]) continue;
@@ -60,14 +65,13 @@ __device__ __forceinline__ void contraction_epilogue(
         const double pkd = a.c0[ch] + (double)spk[chl * kEpiPitch + c] * a.pinv;
         const float pk = (float)pkd;
         const double n2 = a.c1[ch] + (double)sn2[chl * kEpiPitch + c] * a.pinv;
-        const float sg = (float)sqrt(fmax(n2, 0.0) * (double)a.fs_half);
+        // sigma to FP32 rounding (its tolerance is 1e-5)
+        const float sg = sqrtf((float)(fmax(n2, 0.0) * (double)a.fs_half));
         float wn = 0.f;
         if (a.photon) {
           const u32x4 o = philox10(u32x4{(uint32_t)t, (uint32_t)ch, (uint32_t)(a.pix0 + p), 0u},
                                    a.key0, a.key1);
-          float zc, zs;
-          box_muller(o.x, o.y, &zc, &zs);
-          wn = sg * zc;
+          wn = sg * box_muller_cos(o.x, o.y);
         }
         // Kelvin: (P - a_k) / b_k with the offset taken in FP64
         const float v = a.kelvin

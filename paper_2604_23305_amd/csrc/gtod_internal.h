@@ -69,6 +69,7 @@ struct GemmArgs {
   const float* B;        // [3][Kp][Fp] B0, B1', B2 (fp32)
   const uint16_t* Bh;    // [3][Kp][Fp] bf16 hi
   const uint16_t* Bl;    // [3][Kp][Fp] bf16 lo
+  const uint16_t* Bt;    // split responses tiled for the BF16 kernel
   const double* c0;      // [Kp] reference P_KID
   const double* c1;      // [Kp] reference NEP^2
   int Fp, K, Kp;
@@ -271,6 +272,11 @@ void launch_scale_spectra(float* E, float* D, float* W, float* Pref, int Fp,
 void launch_panel(const PanelArgs& a, hipStream_t s);
 void launch_gemm_f32(const GemmArgs& a, hipStream_t s);
 void launch_gemm_bf16(const GemmArgs& a, hipStream_t s);
+// Bytes of the tiled split responses of a Kp x Fp setup, and the kernel
+// that builds them from the hi / lo planes.
+size_t split_tiled_bytes(int Kp, int Fp);
+void launch_tile_split_responses(const uint16_t* Bh, const uint16_t* Bl, uint16_t* Bt,
+                                 int Kp, int Fp, float b2_scale, hipStream_t s);
 void launch_pink_tables(const PinkArgs& a, hipStream_t s);
 void launch_pink_pass1(const PinkArgs& a, hipStream_t s);
 void launch_pink_pass2(const PinkArgs& a, hipStream_t s);

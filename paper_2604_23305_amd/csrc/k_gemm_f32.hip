@@ -198,7 +198,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
   else run(std::integral_constant<int, 1>{});
   __syncthreads();   // every wave is done with the ring before the epilogue reuses it
   float* const spk = ring + (wave >> 1) * kStageFloats + (wave & 1) * kEpiWaveFloats;
-  contraction_epilogue<2, 1>(a, acc, spk, row0 + wave * 32, ch0, live);
+  contraction_epilogue<2, 1, 3>(a, acc, spk, row0 + wave * 32, ch0, live);
 }
 #undef GTOD_WAIT_VM
 #undef GTOD_ISSUE

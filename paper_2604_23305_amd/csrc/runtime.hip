@@ -39,6 +39,7 @@ struct SpecObj {
   float* B = nullptr;
   uint16_t* Bh = nullptr;
   uint16_t* Bl = nullptr;
+  uint16_t* Bt = nullptr;   // Bh / Bl tiled for the split contraction
   double* c0 = nullptr;
   double* c1 = nullptr;
   int pexp = 0;   // the panel carries spectral powers times 2^pexp
@@ -716,6 +717,7 @@ gtod_status gtod_load_filters(gtod_ctx* c, const gtod_spectral_desc* d, int32_t*
   res((void**)&so.B, 3 * Kp * Fp * 4);
   res((void**)&so.Bh, 3 * Kp * Fp * 2);
   res((void**)&so.Bl, 3 * Kp * Fp * 2);
+  res((void**)&so.Bt, split_tiled_bytes((int)Kp, (int)Fp));
   res((void**)&so.c0, Kp * 8);
   res((void**)&so.c1, Kp * 8);
   res((void**)&so.tau64, (size_t)d->n_pwv * F * 8);
@@ -846,6 +848,8 @@ gtod_status gtod_load_filters(gtod_ctx* c, const gtod_spectral_desc* d, int32_t*
     if (e == hipSuccess) {
       launch_scale_spectra(so.E, so.D, so.W, so.Pref, so.Fp,
                            std::ldexp(1.0f, so.pexp), nullptr);
+      launch_tile_split_responses(so.Bh, so.Bl, so.Bt, so.Kp, so.Fp,
+                                  std::ldexp(1.0f, -so.pexp), nullptr);
       e = hipGetLastError();
       if (e == hipSuccess) e = hipDeviceSynchronize();
     }
@@ -1047,6 +1051,7 @@ static gtod_status simulate(gtod_ctx* c, const gtod_job* jobs, int32_t n_jobs,
     ga.B = f.B;
     ga.Bh = f.Bh;
     ga.Bl = f.Bl;
+    ga.Bt = f.Bt;
     ga.c0 = f.c0;
     ga.c1 = f.c1;
     ga.Fp = f.Fp;
