@@ -296,7 +296,8 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
                                a.key0, a.key1);
       float zc, zs;
       box_muller(o.x, o.y, &zc, &zs);
-      const float cj = sc * exp2f(halpha * log2f((float)j * fstep));
+      // power law from the hardware log2 and exp2 (about one ulp each)
+      const float cj = sc * __builtin_amdgcn_exp2f(halpha * __builtin_amdgcn_logf((float)j * fstep));
       x = make_float2(cj * zc, cj * zs);
     }
     buf[at(c, k2)] = x;

@@ -38,26 +38,29 @@ __device__ __forceinline__ float u01(uint32_t o) {
   return (float)(o >> 9) * 1.1920928955078125e-07f + 5.9604644775390625e-08f;
 }
 
-// Box-Muller radius and the angle 2*pi*u1 evaluated as sincospi(2*u1),
-// whose argument is exact.
-__device__ __forceinline__ void box_muller(uint32_t o0, uint32_t o1,
-                                           float* zc, float* zs) {
-  const float r = sqrtf(-2.0f * logf(u01(o0)));
-  float s, c;
-  sincospif(2.0f * u01(o1), &s, &c);
-  *zc = r * c;
-  *zs = r * s;
+// Box-Muller from the hardware transcendentals (about one ulp each): log2
+// of u0 (normal, inside (0, 1)), the square root of -2 ln u0 (inside
+// (0, 34]) and the cosine and sine of u1 revolutions, i.e. of the angle
+// 2 pi u1.  The noise tolerances (the photon-noise term is about 4e-4 of
+// the power; the 1/f series is held to 1e-5 of its rms) are orders of
+// magnitude above these errors.
+__device__ __forceinline__ float bm_radius(uint32_t o0) {
+  // -2 ln u = -2 ln(2) log2(u)
+  return __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01(o0)));
 }
 
-// The cosine half of the Box-Muller pair, r cos(2 pi u1), for the white
-// noise, from the hardware transcendentals (about one ulp each): log2 of
-// u0 (normal, inside (0, 1)), the square root of -2 ln u0 (inside (0, 34])
-// and the cosine of u1 revolutions.  The photon-noise term sigma z is about
-// 4e-4 of the power, so these errors stay far below the TOD tolerance.
+// (r cos 2 pi u1, r sin 2 pi u1)
+__device__ __forceinline__ void box_muller(uint32_t o0, uint32_t o1,
+                                           float* zc, float* zs) {
+  const float r = bm_radius(o0);
+  const float u1 = u01(o1);
+  *zc = r * __builtin_amdgcn_cosf(u1);
+  *zs = r * __builtin_amdgcn_sinf(u1);
+}
+
+// r cos 2 pi u1 only (the white noise)
 __device__ __forceinline__ float box_muller_cos(uint32_t o0, uint32_t o1) {
-  // -2 ln u = -2 ln(2) log2(u)
-  const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u01(o0)));
-  return r * __builtin_amdgcn_cosf(u01(o1));
+  return bm_radius(o0) * __builtin_amdgcn_cosf(u01(o1));
 }
 
 }  // namespace gtod
