@@ -521,6 +521,17 @@ gtod_status gtod_convolve_screen(gtod_ctx* ctx, const double* in, int64_t nx,
  */
 gtod_status gtod_free(gtod_ctx* ctx, int32_t kind, int32_t id);
 
+/*
+ * gtod_release_stream -- free the workspace a stream acquired on its first
+ * gtod_simulate_tod call (panel, 1/f scratch, staging), after waiting for
+ * the work already enqueued on it; its bytes return to the budget.  A
+ * later call on the stream allocates a new workspace.  For callers that
+ * retire streams, so that a long-running process does not keep one
+ * workspace per stream it ever used.
+ * Errors: ENOTFOUND (the stream has no workspace), EDEVICE.
+ */
+gtod_status gtod_release_stream(gtod_ctx* ctx, void* hip_stream);
+
 /* ---- utilities (not part of the simulation path) ---------------------- */
 
 /* Message for the last failed call on ctx (NULL ctx: last init failure). */
@@ -529,9 +540,14 @@ const char* gtod_last_error(const gtod_ctx* ctx);
 /* Bytes currently charged to the budget, and the budget itself. */
 gtod_status gtod_memory(const gtod_ctx* ctx, uint64_t* used, uint64_t* budget);
 
-/* Range events since init: out[0] screen positions clamped to the edge,
- * out[1] PWV values clamped to the table axis.  Synchronises the device. */
-gtod_status gtod_get_counters(gtod_ctx* ctx, uint64_t out[2]);
+/* Range events since init, counted per row (pixel, sample): out[0] screen
+ * positions clamped to the edge, out[1] PWV values clamped to the table
+ * axis, out[2] elevations theta(t) + theta0 + dtheta outside (0, pi),
+ * where the airmass 1/sin(el) of Eq. airmass is undefined (only a
+ * GTOD_SCAN_TRAJ trajectory can reach one; analytic scans are rejected
+ * before launch, and the outputs of such rows are undefined).
+ * Synchronises the device. */
+gtod_status gtod_get_counters(gtod_ctx* ctx, uint64_t out[3]);
 
 /* Reference NEP^2 per channel (W^2/Hz) of a spectral setup: the photon-
  * noise level of the reference spectrum.  out: host [K]. */

@@ -4,7 +4,8 @@ C-ABI (include/gtod.h), with a thin ctypes binding."""
 from .binding import (GtodError, Outputs, ScenarioRun, abi_sizes,  # noqa
                       convolve_screen, convolve_source, counters, far_field,
                       free, load_filters, load_screen, memory,
-                      philox, profile_enable, profile_read, sim_init,
+                      philox, profile_enable, profile_read, release_stream,
+                      sim_init,
                       reduce, simulate_to_disk, simulate_tod,
                       simulate_tod_noalloc, skydip,
                       spec_nep2_ref)

@@ -121,7 +121,8 @@ SYMBOLS = ["gtod_sim_init", "gtod_load_screen", "gtod_load_filters",
            "gtod_philox", "gtod_abi_sizes", "gtod_profile_enable",
            "gtod_profile_read", "gtod_skydip", "gtod_reduce",
            "gtod_simulate_to_disk", "gtod_far_field", "gtod_convolve_source",
-           "gtod_convolve_screen", "gtod_simulate_tod_noalloc"]
+           "gtod_convolve_screen", "gtod_simulate_tod_noalloc",
+           "gtod_release_stream"]
 KERNEL_NAMES = ["panel", "gemm_f32", "gemm_bf16", "pink_pass1", "pink_pass2",
                 "common", "grid", "beam", "src_conv", "screen_conv"]
 MAP_MAX_N = 48
@@ -149,6 +150,7 @@ def load():
     lib.gtod_simulate_tod_noalloc.argtypes = [vp, C.POINTER(Job), C.c_int32,
                                               vp]
     lib.gtod_free.argtypes = [vp, C.c_int32, C.c_int32]
+    lib.gtod_release_stream.argtypes = [vp, vp]
     lib.gtod_last_error.argtypes = [vp]
     lib.gtod_last_error.restype = C.c_char_p
     lib.gtod_memory.argtypes = [vp, C.POINTER(C.c_uint64),

@@ -155,6 +155,14 @@ def simulate_tod_noalloc(ctx, jobs: Sequence[_abi.Job], stream=None):
     _enqueue(_abi.load().gtod_simulate_tod_noalloc, ctx, jobs, stream)
 
 
+def release_stream(ctx, stream):
+    """Free the workspace of a torch stream (or raw hipStream_t handle)
+    after its queued work (gtod_release_stream)."""
+    lib = _abi.load()
+    handle = stream.cuda_stream if hasattr(stream, "cuda_stream") else stream
+    _check(ctx, lib.gtod_release_stream(ctx, C.c_void_p(handle)))
+
+
 def free(ctx, kind=OBJ_CTX, obj_id=0):
     lib = _abi.load()
     _check(ctx, lib.gtod_free(ctx, kind, obj_id))
@@ -171,10 +179,11 @@ def memory(ctx):
 
 
 def counters(ctx):
+    """(screen clamps, table clamps, rows with elevation outside (0, pi))"""
     lib = _abi.load()
-    out = (C.c_uint64 * 2)()
+    out = (C.c_uint64 * 3)()
     _check(ctx, lib.gtod_get_counters(ctx, out))
-    return int(out[0]), int(out[1])
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def spec_nep2_ref(ctx, spec_id, K):

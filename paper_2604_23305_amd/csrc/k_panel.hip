@@ -51,7 +51,7 @@ __device__ inline void clamp_cell(double g, int64_t n, int64_t* cell,
   *w = gc - (double)c;
 }
 
-// Row quantities of row r (FP64 geometry), the PWV output and the clamp
+// Row quantities of row r (FP64 geometry), the PWV output and the range
 // counters; *bucket gets the row's sort bucket.
 __device__ RowInfo row_info(const PanelArgs& a, int64_t r, uint32_t* bucket) {
   RowInfo q{};
@@ -86,7 +86,11 @@ __device__ RowInfo row_info(const PanelArgs& a, int64_t r, uint32_t* bucket) {
   q.li = (int)li;
   q.lw = (float)lw;
   const double el = th + a.theta0 + a.dtheta[p];
-  q.csc = (float)(1.0 / sin(el));
+  const double se = sin(el);
+  // an elevation outside (0, pi) has no airmass (only a user trajectory
+  // can reach one: analytic scans are checked before launch)
+  if (!(se > 0.0)) atomicAdd(&a.counters[2], 1ull);
+  q.csc = (float)(1.0 / se);
   q.src = 0;
   if (a.cube) {
     const double az = phi + a.phi0 + a.dphi[p];

@@ -134,12 +134,14 @@ class Engine:
                  on_done: Optional[Callable[[Request], None]] = None,
                  streams=None):
         """streams: torch.cuda.Stream objects to run on (n_streams is then
-        ignored).  The library keeps a workspace per stream for the life of
-        the context, so engines that follow one another on a context should
-        share their streams."""
+        ignored).  The library keeps a workspace per stream until the
+        stream is released, so engines that follow one another on a context
+        should share their streams; streams the engine makes itself are
+        released by close()."""
         import torch
         self.torch = torch
         self.ctx = ctx
+        self._own_streams = streams is None
         self.streams = list(streams) if streams is not None else [
             torch.cuda.Stream() for _ in range(n_streams)]
         n_streams = len(self.streams)
@@ -158,6 +160,20 @@ class Engine:
         self._rr = 0
         self._t0_event = None
         self._t0_wall = None
+
+    def close(self):
+        """Release the workspaces of the streams this engine created (after
+        their queued work); streams passed in stay with the caller."""
+        if self._own_streams:
+            from . import binding
+            for s in self.streams:
+                try:
+                    binding.release_stream(self.ctx, s)
+                except binding.GtodError as e:
+                    if e.status != _abi.ENOTFOUND:
+                        raise
+            self.streams = []
+            self._own_streams = False
 
     # ------------------------------------------------------------------
     def chunk_len(self, r: Request) -> int:

@@ -170,7 +170,33 @@ def test_table_axis_clamp_matches_oracle(prec):
         _compare(sc, out, ref)
         np.testing.assert_allclose(out.pwv.cpu().numpy(), ref["pwv"],
                                    rtol=1e-7, atol=1e-9)
-        assert g.counters(c) == (int(ref["clamps"]), low + high)
+        assert g.counters(c) == (int(ref["clamps"]), low + high, 0)
+    finally:
+        g.free(c)
+
+
+def test_trajectory_elevation_outside_range_is_counted():
+    """A user trajectory whose elevation leaves (0, pi) has no airmass
+    (Eq. airmass, 1/sin(el)): the rows that do are counted per (pixel,
+    sample) in the third range counter, and every other row still matches
+    the oracle element by element."""
+    from workloads.scenario import Scan
+    sc = tiny_scenario(F=16, K=3, P=2, T=400, scan="stare")
+    traj = np.zeros((400, 2))
+    traj[:, 0] = np.linspace(-20, 20, 400) * gen.ARCSEC
+    traj[:, 1] = np.linspace(-10, 10, 400) * gen.ARCSEC
+    traj[100:150, 1] = -np.pi / 2          # el = pi/3 - pi/2 < 0
+    traj[300:320, 1] = 2.2                 # el = pi/3 + 2.2 > pi
+    sc.scan = Scan("traj", theta0=np.pi / 3, traj=traj)
+    keep = np.r_[0:100, 150:300, 320:400]
+    ref = oracle.tod.simulate(sc, photon_noise=False)
+    c = new_ctx()
+    try:
+        _, out = run_signal(c, sc, photon_noise=False)
+        assert g.counters(c)[2] == sc.n_pix * (50 + 20)
+        e = rel_err(out.p_kid.cpu().numpy()[..., keep], ref["p_kid"][..., keep])
+        report("p_kid (rows with an airmass)", e)
+        assert e.max() <= TOL_PKID
     finally:
         g.free(c)
 

@@ -127,3 +127,27 @@ def test_realtime_arrivals_and_latency(setup):
         assert rec["done_s"] >= rec["arrival_s"]
         assert rec["admit_s"] >= rec["arrival_s"] - 1e-3
     assert s["p99_ms"] >= s["p50_ms"] > 0
+
+
+def test_engine_close_releases_its_stream_workspaces(setup):
+    """An engine that made its own streams returns their workspaces to the
+    context's budget on close(); streams passed in are left alone, and
+    releasing a stream without a workspace is ENOTFOUND."""
+    ctx, scens, runs = setup
+    used0, _ = g.memory(ctx)
+    eng = Engine(ctx, n_streams=3)
+    eng.run(_reqs(runs[:3]), realtime=False)
+    torch.cuda.synchronize()
+    used1, _ = g.memory(ctx)
+    assert used1 > used0
+    eng.close()
+    assert g.memory(ctx)[0] == used0
+    s = torch.cuda.Stream()
+    eng2 = Engine(ctx, streams=[s])
+    eng2.run(_reqs(runs[:1]), realtime=False)
+    eng2.close()
+    assert g.memory(ctx)[0] > used0
+    g.release_stream(ctx, s)
+    assert g.memory(ctx)[0] == used0
+    with pytest.raises(g.GtodError, match="ENOTFOUND"):
+        g.release_stream(ctx, s)
