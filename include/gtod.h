@@ -540,14 +540,20 @@ const char* gtod_last_error(const gtod_ctx* ctx);
 /* Bytes currently charged to the budget, and the budget itself. */
 gtod_status gtod_memory(const gtod_ctx* ctx, uint64_t* used, uint64_t* budget);
 
-/* Range events since init, counted per row (pixel, sample): out[0] screen
+/* Range events since init.  Per row (pixel, sample): out[0] screen
  * positions clamped to the edge, out[1] PWV values clamped to the table
  * axis, out[2] elevations theta(t) + theta0 + dtheta outside (0, pi),
  * where the airmass 1/sin(el) of Eq. airmass is undefined (only a
  * GTOD_SCAN_TRAJ trajectory can reach one; analytic scans are rejected
- * before launch, and the outputs of such rows are undefined).
+ * before launch, and the outputs of such rows are undefined).  Per (row,
+ * frequency bin): out[3] spectra that deviate from the setup's reference
+ * spectrum (ref_pwv_mm, ref_el_rad) by more than 1/8 of their power,
+ * |P - P_ref| > P / 8.  While out[3] stays 0 both contraction precisions
+ * keep P_KID within 1e-6 of exact arithmetic (the split path represents
+ * the deviations with 16 bits); beyond, the error grows with |dP| / P and
+ * a reference closer to the observing conditions restores it.
  * Synchronises the device. */
-gtod_status gtod_get_counters(gtod_ctx* ctx, uint64_t out[3]);
+gtod_status gtod_get_counters(gtod_ctx* ctx, uint64_t out[4]);
 
 /* Reference NEP^2 per channel (W^2/Hz) of a spectral setup: the photon-
  * noise level of the reference spectrum.  out: host [K]. */

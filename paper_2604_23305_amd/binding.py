@@ -179,11 +179,12 @@ def memory(ctx):
 
 
 def counters(ctx):
-    """(screen clamps, table clamps, rows with elevation outside (0, pi))"""
+    """(screen clamps, table clamps, rows with elevation outside (0, pi),
+    (row, bin) elements with |P - P_ref| > P / 8)"""
     lib = _abi.load()
-    out = (C.c_uint64 * 3)()
+    out = (C.c_uint64 * 4)()
     _check(ctx, lib.gtod_get_counters(ctx, out))
-    return int(out[0]), int(out[1]), int(out[2])
+    return tuple(int(v) for v in out)
 
 
 def spec_nep2_ref(ctx, spec_id, K):

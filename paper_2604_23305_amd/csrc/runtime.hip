@@ -555,13 +555,13 @@ gtod_status gtod_sim_init(const gtod_init_desc* d, gtod_ctx** out) {
   c->delta_J = d->delta_J;
   c->eta_pb = d->eta_pb;
   c->t_cmb = d->t_cmb_K;
-  gtod_status st = dev_alloc(c, (void**)&c->counters, 3 * sizeof(unsigned long long));
+  gtod_status st = dev_alloc(c, (void**)&c->counters, 4 * sizeof(unsigned long long));
   if (st != GTOD_OK) {
     g_init_err = c->err;
     delete c;
     return st;
   }
-  if (hipMemset(c->counters, 0, 3 * sizeof(unsigned long long)) != hipSuccess) {
+  if (hipMemset(c->counters, 0, 4 * sizeof(unsigned long long)) != hipSuccess) {
     dev_free(c, c->counters);
     delete c;
     return fail(nullptr, GTOD_EDEVICE, "hipMemset failed");
@@ -1584,13 +1584,13 @@ gtod_status gtod_release_stream(gtod_ctx* c, void* hip_stream) {
   return GTOD_OK;
 }
 
-gtod_status gtod_get_counters(gtod_ctx* c, uint64_t out[3]) {
+gtod_status gtod_get_counters(gtod_ctx* c, uint64_t out[4]) {
   if (!c || !out) return GTOD_EINVAL;
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipDeviceSynchronize());
-  unsigned long long h[3];
+  unsigned long long h[4];
   HIP_TRY(c, hipMemcpy(h, c->counters, sizeof(h), hipMemcpyDeviceToHost));
-  for (int i = 0; i < 3; ++i) out[i] = h[i];
+  for (int i = 0; i < 4; ++i) out[i] = h[i];
   return GTOD_OK;
 }
 

@@ -126,7 +126,7 @@ class TestC3:
 
     def test_no_clamps_and_finite(self, c3):
         sc, ctx, run, out, pink = c3
-        assert g.counters(ctx) == (0, 0, 0)
+        assert g.counters(ctx) == (0, 0, 0, 0)
         assert bool(torch.isfinite(out.tod).all())
         assert bool(torch.isfinite(pink).all())
 
@@ -159,7 +159,7 @@ class TestC4:
 
     def test_no_clamps_and_finite(self, c4):
         sc, ctx, run, out, pink = c4
-        assert g.counters(ctx) == (0, 0, 0)
+        assert g.counters(ctx) == (0, 0, 0, 0)
         assert bool(torch.isfinite(out.tod).all())
         assert bool(torch.isfinite(pink).all())
 
