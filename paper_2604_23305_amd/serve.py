@@ -28,6 +28,7 @@ caller loads them (load_screen / load_filters) and passes their ids.
 from __future__ import annotations
 
 import collections
+import json
 import time
 from dataclasses import dataclass, field
 from typing import Callable, Dict, List, Optional
@@ -132,12 +133,13 @@ class Engine:
     def __init__(self, ctx, n_streams=4, hbm_budget_bytes=64 << 30,
                  chunk_rows=1 << 18, max_inflight=2, keep_outputs=False,
                  on_done: Optional[Callable[[Request], None]] = None,
-                 streams=None):
+                 streams=None, log_path: Optional[str] = None):
         """streams: torch.cuda.Stream objects to run on (n_streams is then
         ignored).  The library keeps a workspace per stream until the
         stream is released, so engines that follow one another on a context
         should share their streams; streams the engine makes itself are
-        released by close()."""
+        released by close().  log_path: append one JSON line per completed
+        request (its record in stats.records) to this file."""
         import torch
         self.torch = torch
         self.ctx = ctx
@@ -157,6 +159,7 @@ class Engine:
         self.pending: collections.deque = collections.deque()
         self.done: List[Request] = []
         self.stats = EngineStats()
+        self.log_path = log_path
         self._rr = 0
         self._t0_event = None
         self._t0_wall = None
@@ -301,13 +304,17 @@ class Engine:
                 t_gpu = self._t0_event.elapsed_time(r.done_event) / 1e3
                 r.t_done = t_gpu
                 self.used -= r.out_bytes
-                self.stats.records.append(dict(
+                rec = dict(
                     rid=r.rid, arrival_s=r.arrival_s, admit_s=r.t_admit,
                     first_issue_s=r.t_first, done_s=t_gpu,
                     latency_ms=(t_gpu - r.arrival_s) * 1e3,
                     det_samples=r.det_samples, bytes=r.out_bytes,
                     n_pix=r.n_pix, K=r.K, t_total=r.t_total,
-                    stream=r.stream_idx))
+                    stream=r.stream_idx)
+                self.stats.records.append(rec)
+                if self.log_path:
+                    with open(self.log_path, "a") as f:
+                        f.write(json.dumps(rec, default=float) + "\n")
                 if self.on_done:
                     self.on_done(r)
                 if not self.keep_outputs:

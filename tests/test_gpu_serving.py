@@ -151,3 +151,18 @@ def test_engine_close_releases_its_stream_workspaces(setup):
     assert g.memory(ctx)[0] == used0
     with pytest.raises(g.GtodError, match="ENOTFOUND"):
         g.release_stream(ctx, s)
+
+
+def test_engine_jsonl_log(setup, tmp_path):
+    """With log_path the engine appends one JSON record per completed
+    request, the same records stats.records holds."""
+    import json
+    ctx, scens, runs = setup
+    log = tmp_path / "requests.jsonl"
+    eng = Engine(ctx, n_streams=2, log_path=str(log))
+    stats = eng.run(_reqs(runs[:4]), realtime=False)
+    eng.close()
+    lines = [json.loads(x) for x in log.read_text().splitlines()]
+    assert len(lines) == 4
+    assert sorted(r["rid"] for r in lines) == [0, 1, 2, 3]
+    assert lines == stats.records
