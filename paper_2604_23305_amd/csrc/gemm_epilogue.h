@@ -37,6 +37,21 @@ __device__ __forceinline__ void contraction_epilogue(
   for (int i = 0; i < NI; ++i) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
+      const int64_t row = row_base + j * 32 + c;
+      const int pl = (int)(row / a.Tpad);
+      const int tl = (int)(row % a.Tpad);
+      const bool valid = live[i] && pl < a.n_pix && tl < a.Tc;
+      const int p = a.p0 + pl;
+      const int64_t t = a.t0 + tl;
+      const int chb = ch_base + i * 32;
+      const int64_t off0 = ((int64_t)p * a.K + chb + h) * a.out_ld + (t - a.out_t0);
+      // when adding into the TOD, its 16 values are loaded first, so that
+      // they are in flight together and during the LDS staging below
+      float prev[16];
+#pragma unroll
+      for (int s = 0; s < 16; ++s)
+        prev[s] = (a.accumulate && valid && chb + 2 * s + h < a.K)
+                      ? a.tod[off0 + 2 * s * a.out_ld] : 0.f;
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
@@ -48,14 +63,7 @@ __device__ __forceinline__ void contraction_epilogue(
           sn2[chl * kEpiPitch + c] = acc[1][i][j][e];
       }
       __syncthreads();
-      if (!live[i]) continue;
-      const int64_t row = row_base + j * 32 + c;
-      const int pl = (int)(row / a.Tpad);
-      const int tl = (int)(row % a.Tpad);
-      if (pl >= a.n_pix || tl >= a.Tc) continue;
-      const int p = a.p0 + pl;
-      const int64_t t = a.t0 + tl;
-      const int chb = ch_base + i * 32;
+      if (!valid) continue;
       for (int s = 0; s < 16; ++s) {
         const int chl = 2 * s + h;
         const int ch = chb + chl;
@@ -77,8 +85,8 @@ __device__ __forceinline__ void contraction_epilogue(
         const float v = a.kelvin
             ? (float)(((pkd - a.kel_a[ch]) + (double)wn) * a.kel_ib[ch])
             : pk + wn;
-        const int64_t off = ((int64_t)p * a.K + ch) * a.out_ld + (t - a.out_t0);
-        if (a.accumulate) a.tod[off] += v; else a.tod[off] = v;
+        const int64_t off = off0 + 2 * s * a.out_ld;
+        a.tod[off] = a.accumulate ? prev[s] + v : v;
         if (a.p_kid) a.p_kid[off] = pk;
         if (a.sigma) a.sigma[off] = sg;
       }

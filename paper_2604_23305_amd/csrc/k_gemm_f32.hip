@@ -153,50 +153,86 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
   // wave index and ring address as wave-uniform (scalar) values for M0
   const int wave_s = __builtin_amdgcn_readfirstlane(wave);
   const uint32_t lds0 = __builtin_amdgcn_readfirstlane(lds_addr(ring));
-  GTOD_ISSUE(lds0, 0)
-  if (n_chunks > 1) GTOD_ISSUE(lds0 + 4u * kStageFloats, 1)
-  // NI live 32-channel tiles (uniform over the workgroup): every LDS read
-  // of a chunk is issued before its MFMAs
+  // stage of chunk c is c mod 3; chunks 0-2 are issued before the loop
+#pragma unroll
+  for (int c0 = 0; c0 < 3; ++c0)
+    if (c0 < n_chunks) GTOD_ISSUE(lds0 + 4u * kStageFloats * c0, c0)
+  // NI live 32-channel tiles (uniform over the workgroup)
   auto run = [&](auto ni_c) {
     constexpr int NI = decltype(ni_c)::value;
-    int sr = 0;   // stage of chunk kc
-    for (int kc = 0; kc < n_chunks; ++kc) {
-      if (kc + 1 < n_chunks) { GTOD_WAIT_VM(5); } else { GTOD_WAIT_VM(0); }
-      __builtin_amdgcn_s_barrier();
-      const int sw = sr == 0 ? 2 : sr - 1;   // stage of chunk kc + 2
-      if (kc + 2 < n_chunks) GTOD_ISSUE(lds0 + 4u * kStageFloats * sw, kc + 2)
-      const float* sD = ring + kStageFloats * sr;
+    constexpr int NR = 1 + 3 * NI;   // LDS reads per half chunk
+    typedef float4 Ops[NR];          // dP, then the responses (i, m)
+    // the operands of half hs of a chunk: lane half h takes bin quad 2h + hs
+    auto read_half = [&](int st, int hs, Ops& o) {
+      const float* sD = ring + kStageFloats * st;
       const float* sB = sD + MT * KC;
-      float4 dv[2], bv[2][NI][3];
+      const int q = 2 * h + hs;
+      o[0] = *reinterpret_cast<const float4*>(&sD[rd * KC + 4 * (q ^ swz(rd))]);
 #pragma unroll
-      for (int hs = 0; hs < 2; ++hs) {
-        const int q = 2 * h + hs;
-        dv[hs] = *reinterpret_cast<const float4*>(&sD[rd * KC + 4 * (q ^ swz(rd))]);
+      for (int i = 0; i < NI; ++i)
 #pragma unroll
-        for (int i = 0; i < NI; ++i)
+        for (int m = 0; m < 3; ++m) {
+          const int rb = m * NT + i * 32 + c;
+          o[1 + 3 * i + m] = *reinterpret_cast<const float4*>(&sB[rb * KC + 4 * (q ^ swz(rb))]);
+        }
+    };
+    auto mfma_half = [&](const Ops& o) {
+      float dsq[4];
 #pragma unroll
-          for (int m = 0; m < 3; ++m) {
-            const int rb = m * NT + i * 32 + c;
-            bv[hs][i][m] = *reinterpret_cast<const float4*>(&sB[rb * KC + 4 * (q ^ swz(rb))]);
-          }
+      for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = o[0][s4] * o[0][s4];
+#pragma unroll
+      for (int i = 0; i < NI; ++i)
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+          acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(o[1 + 3 * i][s4], o[0][s4], acc[0][i][0], 0, 0, 0);
+          acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(o[2 + 3 * i][s4], o[0][s4], acc[1][i][0], 0, 0, 0);
+          acc[2][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(o[3 + 3 * i][s4], dsq[s4], acc[2][i][0], 0, 0, 0);
+        }
+    };
+    // the next half chunk's LDS reads go early in the MFMA block, one after
+    // each MFMA, so that they have landed when the next block starts
+    auto interleave = [&] {
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
       }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int hs = 0; hs < 2; ++hs) {
-        float dsq[4];
-#pragma unroll
-        for (int s4 = 0; s4 < 4; ++s4) dsq[s4] = dv[hs][s4] * dv[hs][s4];
-#pragma unroll
-        for (int i = 0; i < NI; ++i)
-#pragma unroll
-          for (int s4 = 0; s4 < 4; ++s4) {
-            acc[0][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[hs][i][0][s4], dv[hs][s4], acc[0][i][0], 0, 0, 0);
-            acc[1][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[hs][i][1][s4], dv[hs][s4], acc[1][i][0], 0, 0, 0);
-            acc[2][i][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(bv[hs][i][2][s4], dsq[s4], acc[2][i][0], 0, 0, 0);
-          }
-      }
-      sr = sr == 2 ? 0 : sr + 1;
+      __builtin_amdgcn_sched_group_barrier(0x008, 12 * NI - NR, 0);
+    };
+    // Between the halves of chunk kc each wave waits for its own LDS reads
+    // and for its DMA of chunk kc + 1, then passes a barrier: chunk kc + 1
+    // is visible and no wave still reads stage kc mod 3, which takes chunk
+    // kc + 3.
+    auto sync = [&](int kc) {
+      __builtin_amdgcn_sched_barrier(0);    // keep the wait after the MFMAs
+      __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
+      if (kc + 2 < n_chunks) { GTOD_WAIT_VM(5); } else { GTOD_WAIT_VM(0); }
+      __builtin_amdgcn_s_barrier();
+      if (kc + 3 < n_chunks) GTOD_ISSUE(lds0 + 4u * kStageFloats * (kc % 3), kc + 3)
+    };
+    // Every MFMA block runs with the next half chunk's LDS reads between
+    // its MFMAs, into the other register set.
+    Ops oa, ob;
+    if (n_chunks > 2) { GTOD_WAIT_VM(10); }
+    else if (n_chunks > 1) { GTOD_WAIT_VM(5); }
+    else { GTOD_WAIT_VM(0); }
+    __builtin_amdgcn_s_barrier();
+    read_half(0, 0, oa);
+    int kc = 0;
+    for (; kc + 1 < n_chunks; ++kc) {
+      read_half(kc % 3, 1, ob);
+      mfma_half(oa);
+      interleave();
+      sync(kc);
+      read_half((kc + 1) % 3, 0, oa);
+      mfma_half(ob);
+      interleave();
     }
+    read_half(kc % 3, 1, ob);
+    mfma_half(oa);
+    interleave();
+    sync(kc);
+    mfma_half(ob);
   };
   if (live[1]) run(std::integral_constant<int, 2>{});
   else run(std::integral_constant<int, 1>{});

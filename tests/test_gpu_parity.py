@@ -73,11 +73,12 @@ def test_c1_full_parity(ctx, noise):
 
 @pytest.mark.parametrize("prec", [g.PREC_FP32, g.PREC_SPLIT_BF16])
 @pytest.mark.parametrize("filt", ["filterbank", "lorentz", "matrix"])
-@pytest.mark.parametrize("shape", [(8, 3, 2, 5), (37, 33, 3, 131),
-                                   (100, 130, 2, 300)])
+@pytest.mark.parametrize("shape", [(8, 3, 2, 5), (29, 70, 2, 200),
+                                   (37, 33, 3, 131), (100, 130, 2, 300)])
 def test_tiny_and_ragged_shapes(ctx, filt, shape, prec):
     """Shapes that leave ragged F, K and T tiles; every cascade kind; both
-    contraction kernels (a K tail of one or two 32-channel tiles)."""
+    contraction kernels (a K tail of one or two 32-channel tiles, or of a
+    partly live channel group)."""
     F, K, P, T = shape
     sc = tiny_scenario(F=F, K=K, P=P, T=T, filt=filt,
                        stages=configs.cascade_table2())
@@ -268,6 +269,25 @@ def test_accumulate_adds_into_tod(ctx):
     np.testing.assert_allclose(out.tod.cpu().numpy(),
                                out.p_kid.cpu().numpy().astype(np.float64) + 1e-12,
                                rtol=1e-6)
+
+
+@pytest.mark.parametrize("prec", [g.PREC_FP32, g.PREC_SPLIT_BF16])
+def test_accumulate_is_one_fp32_add(ctx, prec):
+    """Adding into an existing TOD gives, element by element, exactly the
+    FP32 sum of the old value and the TOD the same job writes on its own
+    (noise on; 70 channels leave a partly live channel group and 32-channel
+    tile, whose dead rows must neither be loaded nor stored)."""
+    sc = tiny_scenario(F=40, K=70, P=3, T=700, stages=configs.cascade_table2())
+    run, ref = run_signal(ctx, sc, precision=prec)
+    out = run.alloc()
+    gen_ = torch.Generator(device="cpu").manual_seed(5)
+    prev = torch.randn(out.tod.shape, generator=gen_).float().cuda()
+    out.tod.copy_(prev)
+    g.simulate_tod(ctx, [run.signal_job(out, precision=prec, accumulate=True)])
+    torch.cuda.synchronize()
+    want = (prev + ref.tod).cpu().numpy()
+    got = out.tod.cpu().numpy()
+    assert np.array_equal(got, want), float(np.abs(got - want).max())
 
 
 def test_uniform_screen_gives_constant_tod(ctx):
