@@ -14,28 +14,28 @@
 //
 // Workgroup: 4 waves along time, each 32 samples x both (or the one live)
 // 32-channel tiles of the group: 96 accumulator registers (AGPRs) beside
-// 80 VGPRs, and 60 KB of LDS, so two workgroups share a CU and one's
+// 116 VGPRs, and 60 KB of LDS, so two workgroups share a CU and one's
 // barriers and epilogue overlap the other's MFMAs.
 //
 // Operand staging: depth chunks of 16 frequency bins go straight from
 // global memory into a three-stage LDS ring with global_load_lds_dwordx4
-// (no register staging), two chunks ahead of the MFMAs.  A stage holds the
-// panel [128][16] and the three responses [3][64][16] in unpadded 64-byte
-// rows; the 16-byte slot of bin quad q in row r is q ^ swz(r), which puts
-// the 16-byte reads of 32 consecutive rows into distinct bank groups.
-// The DMA is issued from inline assembly: the compiler does not know that
-// it writes LDS, so it does not wait for it before every LDS read of the
-// other stages.  Ordering comes from the kernel itself: before chunk c is
-// read, each wave waits until at most the 5 DMAs of chunk c + 1 are in
-// flight, and a barrier makes every wave's part of chunk c visible; the
-// stage that chunk c + 2 overwrites was last read before that barrier.
-// Every LDS read of a chunk is issued before its first MFMA, so one LDS
-// latency per chunk is exposed, not one per operand group; the main loop
-// is instantiated for one and for two live 32-channel tiles, so that no
-// branch splits the reads from the MFMAs.
-//
-// Tile index -> workgroup mapping keeps the channel groups of one time tile
-// on the same XCD so the panel tile is fetched once into that XCD's L2.
+// (no register staging), issued three chunks ahead of the MFMAs.  A stage
+// holds the panel [128][16] and the three responses [3][64][16] in
+// unpadded 64-byte rows; the 16-byte slot of bin quad q in row r is
+// q ^ swz(r), which puts the 16-byte reads of 32 consecutive rows into
+// distinct bank groups.  The DMA is issued from inline assembly: the
+// compiler does not know that it writes LDS, so it does not wait for it
+// before every LDS read of the other stages.
+// Each wave reads a chunk in two halves (bin quads 2h + hs for lane half
+// h) into two register sets, and every MFMA block runs with the LDS reads
+// of the next half chunk placed between its MFMAs, so no LDS latency is
+// exposed.  Between the two halves of chunk c each wave waits for its own
+// LDS reads and for its DMAs of chunk c + 1, then passes the one barrier
+// of the chunk: chunk c + 1 is visible and no wave reads stage c mod 3
+// any more, which then takes chunk c + 3.
+// Tile index -> workgroup mapping: block b runs on XCD b mod 8, so the
+// channel groups of one time tile are given blocks of the same XCD and
+// can share the panel tile in its L2.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
