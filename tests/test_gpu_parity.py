@@ -409,6 +409,44 @@ def test_pink_accumulate_adds_into_tod(ctx, T, offset):
     assert torch.equal(tod.cpu(), expect)
 
 
+def test_pink_batches_are_invisible(ctx):
+    """A workspace too small for all series at once: the 111 series of
+    40000 samples (two-pass transforms, 16 columns) go in 5 batches of 27
+    (the last one of 3).  The TOD, added into random values, is
+    bit-identical to the one-batch run of a large workspace; three series,
+    one per pixel and in different batches, match the oracle."""
+    T = 40000
+    sc = tiny_scenario(F=16, K=37, P=3, T=T)
+    sc.pink_alpha = np.linspace(0.5, 2.0, sc.K)
+    nep2 = oracle.tod.reference_nep2(sc)
+    A = opk.amplitude(nep2, sc.pink_alpha, sc.pink_knee_hz)
+    refs = {(p, k): opk.series(sc.seed, p, k, A[k], sc.pink_alpha[k], T,
+                               sc.f_sample_hz)
+            for p, k in ((0, 5), (1, 20), (2, 36))}
+    # values at the series' own level, so that subtracting them again
+    # costs only rounding
+    level = float(np.mean([r.std() for r in refs.values()]))
+    base = level * torch.randn((sc.n_pix, sc.K, T),
+                               generator=torch.Generator().manual_seed(9))
+    outs = []
+    for ws in (28 << 20, 1 << 30):
+        c = new_ctx(workspace_bytes=ws)
+        try:
+            run = g.ScenarioRun(c, sc)
+            tod = base.to("cuda")
+            g.simulate_tod(c, [run.pink_job(tod, accumulate=True)])
+            torch.cuda.synchronize()
+            outs.append(tod.cpu())
+        finally:
+            g.free(c)
+    assert torch.equal(outs[0], outs[1])
+    got = outs[0].double().numpy() - base.double().numpy()
+    for (p, k), ref in refs.items():
+        err = np.abs(got[p, k] - ref).max() / ref.std()
+        print(f"  pink p={p} k={k}: max err / rms {err:.3e}", flush=True)
+        assert err <= TOL_PINK
+
+
 @pytest.mark.parametrize("T,K", [(2**21 + 5, 2), (2**25 - 3, 1)])
 def test_pink_long_series(ctx, T, K):
     """Long series: four-step splits with 512 and with 4096 columns (the
