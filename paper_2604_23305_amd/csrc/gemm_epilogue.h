@@ -10,7 +10,10 @@
 // (kEpiWaveFloats floats at spk, distinct for each wave) with
 // static register indices, then read back by a compact loop in which lane
 // l handles sample (l mod 32) of channel rows 2s + l/32: stores are runs of
-// 32 consecutive samples.
+// 32 consecutive samples.  The slice belongs to one wave, whose LDS
+// accesses complete in order, so the waves of a workgroup go through the
+// epilogue without barriers (the kernel has one before it, after the last
+// read of its operand ring).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -52,7 +55,7 @@ __device__ __forceinline__ void contraction_epilogue(
       for (int s = 0; s < 16; ++s)
         prev[s] = (a.accumulate && valid && chb + 2 * s + h < a.K)
                       ? a.tod[off0 + 2 * s * a.out_ld] : 0.f;
-      __syncthreads();
+      __builtin_amdgcn_wave_barrier();
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int chl = 8 * (e >> 2) + 4 * h + (e & 3);
@@ -62,7 +65,7 @@ __device__ __forceinline__ void contraction_epilogue(
         else
           sn2[chl * kEpiPitch + c] = acc[1][i][j][e];
       }
-      __syncthreads();
+      __builtin_amdgcn_wave_barrier();
       if (!valid) continue;
       for (int s = 0; s < 16; ++s) {
         const int chl = 2 * s + h;

@@ -60,15 +60,18 @@ __device__ __forceinline__ uint32_t lds_addr(float* p) {
   return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float*)p;
 }
 
-// One wave-wide direct-to-LDS load: lane i moves the 16 bytes at g to LDS
-// byte address m0 + 16 i (m0 uniform).  M0 is a reserved register the
-// compiler does not save around inline assembly; no other code in this
-// kernel uses it.  The s_nop covers the M0 write -> LDS DMA hazard.
-__device__ __forceinline__ void dma16(const float* g, uint32_t m0) {
+// One wave-wide direct-to-LDS load: lane i moves the 16 bytes at base +
+// voff (base wave-uniform, in scalar registers; voff the lane's byte
+// offset) to LDS byte address m0 + 16 i (m0 uniform).  Advancing base is
+// scalar arithmetic, so the loop spends no vector instructions on DMA
+// addresses.  M0 is a reserved register the compiler does not save around
+// inline assembly; no other code in this kernel uses it.  The s_nop covers
+// the M0 write -> LDS DMA hazard.
+__device__ __forceinline__ void dma16(const float* base, uint32_t voff, uint32_t m0) {
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm"
-  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
-               :: "s"(m0), "v"(g) : "memory", "m0");
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2"
+               :: "s"(m0), "v"(voff), "s"(base) : "memory", "m0");
 #pragma clang diagnostic pop
 }
 
@@ -113,33 +116,39 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
   // Direct-to-LDS loads: one wave instruction moves 16 rows x 16 bins (64
   // lanes x 16 bytes) into 1 KB of LDS, lane i to offset 16 i.  Lane i
   // takes row i / 4 of its block and the bin quad (i % 4) ^ swz(row).
+  // Sources are a wave-uniform base plus a 32-bit lane offset (a response
+  // plane is below 4 GiB, which the spectral setup checks).
   const int lr = lane >> 2, lq = lane & 3;
-  // panel: wave w moves rows 32 w + 16 q + lr, q = 0, 1
-  const float* gp[2];
+  const int wave_s = __builtin_amdgcn_readfirstlane(wave);
+  // panel: wave w moves rows 32 w + 16 q + lr, q = 0, 1, from the tile's rows
+  const float* const gp = a.panel + row0 * Fp;
+  uint32_t vp[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int r = wave * 32 + q * 16 + lr;
-    gp[q] = a.panel + (row0 + r) * Fp + 4 * (lq ^ swz(r));
+    vp[q] = (uint32_t)(4 * ((int64_t)r * Fp + 4 * (lq ^ swz(r))));
   }
   // responses: wave w moves blocks u = 3 w + q: matrix u / 4, channels
   // 16 (u % 4) + lr (clamped into the padded matrix; dead rows are unused)
   const float* gb[3];
+  uint32_t vb[3];
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
-    const int u = wave * 3 + q;
+    const int u = wave_s * 3 + q;
     const int m = u >> 2, r = ((u & 3) << 4) + lr;
     const int gch = min(ch0 + r, a.Kp - 1);
-    gb[q] = a.B + m * KF + (int64_t)gch * Fp + 4 * (lq ^ swz(m * NT + r));
+    gb[q] = a.B + m * KF;
+    vb[q] = (uint32_t)(4 * ((int64_t)gch * Fp + 4 * (lq ^ swz(m * NT + r))));
   }
   // issue chunk `chunk` into the stage at LDS byte address ST
 #define GTOD_ISSUE(ST, chunk)                                                 \
   {                                                                           \
     const int k0_ = (chunk) * KC;                                             \
     _Pragma("unroll") for (int q = 0; q < 2; ++q)                             \
-      dma16(gp[q] + k0_, (ST) + 4u * ((wave_s * 32 + q * 16) * KC));         \
+      dma16(gp + k0_, vp[q], (ST) + 4u * ((wave_s * 32 + q * 16) * KC));     \
     _Pragma("unroll") for (int q = 0; q < 3; ++q) {                           \
       const int u = wave_s * 3 + q;                                           \
-      dma16(gb[q] + k0_,                                                      \
+      dma16(gb[q] + k0_, vb[q],                                               \
             (ST) + 4u * (MT * KC + ((u >> 2) * NT + ((u & 3) << 4)) * KC));  \
     }                                                                         \
   }
@@ -150,8 +159,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
 
   const int n_chunks = a.Fp / KC;
   const int rd = wave * 32 + c;
-  // wave index and ring address as wave-uniform (scalar) values for M0
-  const int wave_s = __builtin_amdgcn_readfirstlane(wave);
+  // ring address as a wave-uniform (scalar) value for M0
   const uint32_t lds0 = __builtin_amdgcn_readfirstlane(lds_addr(ring));
   // stage of chunk c is c mod 3; chunks 0-2 are issued before the loop
 #pragma unroll
@@ -203,35 +211,44 @@ __global__ __launch_bounds__(256, 2) void k_gemm_f32(GemmArgs a) {
     // and for its DMA of chunk kc + 1, then passes a barrier: chunk kc + 1
     // is visible and no wave still reads stage kc mod 3, which takes chunk
     // kc + 3.
-    auto sync = [&](int kc) {
+    auto sync = [&](int kc, int st) {
       __builtin_amdgcn_sched_barrier(0);    // keep the wait after the MFMAs
       __builtin_amdgcn_s_waitcnt(0xc07f);   // lgkmcnt(0)
       if (kc + 2 < n_chunks) { GTOD_WAIT_VM(5); } else { GTOD_WAIT_VM(0); }
       __builtin_amdgcn_s_barrier();
-      if (kc + 3 < n_chunks) GTOD_ISSUE(lds0 + 4u * kStageFloats * (kc % 3), kc + 3)
+      if (kc + 3 < n_chunks) GTOD_ISSUE(lds0 + 4u * kStageFloats * st, kc + 3)
     };
     // Every MFMA block runs with the next half chunk's LDS reads between
-    // its MFMAs, into the other register set.
+    // its MFMAs, into the other register set.  st = kc mod 3 is a constant
+    // in the main loop (unrolled by the ring depth), so LDS addresses are
+    // a base register plus immediate offsets.
     Ops oa, ob;
+    auto chunk = [&](int kc, int st) {
+      __builtin_amdgcn_sched_barrier(0);    // one MFMA block per scheduling region
+      read_half(st, 1, ob);
+      mfma_half(oa);
+      interleave();
+      sync(kc, st);
+      read_half(st == 2 ? 0 : st + 1, 0, oa);
+      mfma_half(ob);
+      interleave();
+    };
     if (n_chunks > 2) { GTOD_WAIT_VM(10); }
     else if (n_chunks > 1) { GTOD_WAIT_VM(5); }
     else { GTOD_WAIT_VM(0); }
     __builtin_amdgcn_s_barrier();
     read_half(0, 0, oa);
     int kc = 0;
-    for (; kc + 1 < n_chunks; ++kc) {
-      read_half(kc % 3, 1, ob);
-      mfma_half(oa);
-      interleave();
-      sync(kc);
-      read_half((kc + 1) % 3, 0, oa);
-      mfma_half(ob);
-      interleave();
+    for (; kc + 3 < n_chunks; kc += 3) {
+      chunk(kc, 0);
+      chunk(kc + 1, 1);
+      chunk(kc + 2, 2);
     }
+    for (; kc + 1 < n_chunks; ++kc) chunk(kc, kc % 3);
     read_half(kc % 3, 1, ob);
     mfma_half(oa);
     interleave();
-    sync(kc);
+    sync(kc, kc % 3);
     mfma_half(ob);
   };
   if (live[1]) run(std::integral_constant<int, 2>{});
