@@ -169,9 +169,9 @@ typedef struct gtod_stage {
  *   (gtod_job.pink_knee_hz).
  * All pointers are host memory.  Synchronous.
  * Errors: EINVAL (F < 1, K < 1, n_pwv < 2, bad mode/kind, non-positive
- * weights or dpwv, or a padded response plane of 4 GiB or more: F and K
- * rounded up to multiples of 32, times 4 bytes), EBUDGET, ENOMEM,
- * EDEVICE.
+ * weights or dpwv, a padded response plane of 4 GiB or more -- F and K
+ * rounded up to multiples of 32, times 4 bytes -- or F rounded up to a
+ * multiple of 32 above 4194303), EBUDGET, ENOMEM, EDEVICE.
  */
 typedef struct gtod_spectral_desc {
   int32_t F;

@@ -81,15 +81,17 @@ __device__ __forceinline__ uint32_t lds_addr(void* p) {
   return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) char*)p;
 }
 
-// One wave-wide direct-to-LDS load: lane i moves the 16 bytes at g to LDS
-// byte address m0 + 16 i (m0 uniform).  M0 is a reserved register the
-// compiler does not save around inline assembly; no other code in this
-// kernel uses it.  The s_nop covers the M0 write -> LDS DMA hazard.
-__device__ __forceinline__ void dma16(const void* g, uint32_t m0) {
+// One wave-wide direct-to-LDS load: lane i moves the 16 bytes at base +
+// voff (base wave-uniform, in scalar registers; voff the lane's byte
+// offset) to LDS byte address m0 + 16 i (m0 uniform).  Advancing base is
+// scalar arithmetic.  M0 is a reserved register the compiler does not
+// save around inline assembly; no other code in this kernel uses it.  The
+// s_nop covers the M0 write -> LDS DMA hazard.
+__device__ __forceinline__ void dma16(const void* base, uint32_t voff, uint32_t m0) {
 #pragma clang diagnostic push
 #pragma clang diagnostic ignored "-Winline-asm"
-  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, off"
-               :: "s"(m0), "v"(g) : "memory", "m0");
+  asm volatile("s_mov_b32 m0, %0\n\ts_nop 0\n\tglobal_load_lds_dwordx4 %1, %2"
+               :: "s"(m0), "v"(voff), "s"(base) : "memory", "m0");
 #pragma clang diagnostic pop
 }
 
@@ -188,31 +190,35 @@ __global__ __launch_bounds__(512, 1) void k_gemm_bf16(GemmArgs a) {
   const int64_t Fp = a.Fp;
   const int n_steps = a.Fp / KC;
   const int wave_s = __builtin_amdgcn_readfirstlane(wave);
+  // DMA sources are a wave-uniform base plus a 32-bit lane offset (the
+  // spectral setup keeps 256 panel rows below 4 GiB).
   // panel DMA: wave w moves blocks w and w + 8, rows 16 block + lane / 4,
   // lane taking bin quad (lane % 4) ^ swz(row)
-  const float* gp[2];
+  const float* const gp = a.panel + row0 * Fp;
+  uint32_t vp[2];
 #pragma unroll
   for (int q = 0; q < 2; ++q) {
     const int r = (wave + 8 * q) * 16 + (lane >> 2);
     const int64_t gr = min(row0 + r, n_rows - 1);
-    gp[q] = a.panel + gr * Fp + 4 * ((lane & 3) ^ swz(r));
+    vp[q] = (uint32_t)(4 * ((gr - row0) * Fp + 4 * ((lane & 3) ^ swz(r))));
   }
   // response DMA: wave w moves the 1 KB blocks w, w + 8 and (waves 0-3)
   // w + 16 of the stage's contiguous image
   const int n_rb = wave_s < kRespBlocks - 2 * kWaves ? 3 : 2;
-  const char* gt = reinterpret_cast<const char*>(a.Bt) +
-                   (size_t)cg * n_steps * kRespBytes + wave * 1024 + lane * 16;
+  const char* const gt = reinterpret_cast<const char*>(a.Bt) +
+                         (size_t)cg * n_steps * kRespBytes + wave_s * 1024;
+  const uint32_t vt = (uint32_t)lane * 16u;
   const uint32_t lds0 = __builtin_amdgcn_readfirstlane(lds_addr(ring));
   // issue step `st` into the stage at LDS byte address S
 #define GTOD_ISSUE(S, st)                                                     \
   {                                                                           \
     const int k0_ = (st) * KC;                                                \
     _Pragma("unroll") for (int q = 0; q < 2; ++q)                             \
-      dma16(gp[q] + k0_, (S) + (uint32_t)((wave_s + 8 * q) * 1024));          \
+      dma16(gp + k0_, vp[q], (S) + (uint32_t)((wave_s + 8 * q) * 1024));      \
     const char* t_ = gt + (size_t)(st) * kRespBytes;                          \
     _Pragma("unroll") for (int q = 0; q < 3; ++q)                             \
       if (q < n_rb)                                                           \
-        dma16(t_ + q * 8 * 1024,                                              \
+        dma16(t_ + q * 8 * 1024, vt,                                          \
               (S) + (uint32_t)(kPanelBytes + (wave_s + 8 * q) * 1024));       \
   }
 
@@ -227,14 +233,15 @@ __global__ __launch_bounds__(512, 1) void k_gemm_bf16(GemmArgs a) {
   // same steps and barriers)
   auto run = [&](auto ni_c) {
     constexpr int NI = decltype(ni_c)::value;
-    for (int s = 0; s < n_steps; ++s) {
-      const int sr = s & (kStages - 1);   // stage of step s
+    // step s from stage sr = s mod 4; a constant in the main loop below
+    // (unrolled by the ring depth), so LDS addresses are immediates
+    auto step = [&](int s, int sr) {
       if (s + 2 < n_steps) { GTOD_WAIT_VM(8); }
       else if (s + 1 < n_steps) { GTOD_WAIT_VM(4); }
       else { GTOD_WAIT_VM(0); }
       __builtin_amdgcn_s_barrier();
       if (s + 3 < n_steps)
-        GTOD_ISSUE(lds0 + (uint32_t)(kStageBytes * ((s + 3) & (kStages - 1))), s + 3)
+        GTOD_ISSUE(lds0 + (uint32_t)(kStageBytes * ((sr + 3) & (kStages - 1))), s + 3)
       const char* sP = ring + kStageBytes * sr;
       const char* sB = sP + kPanelBytes;
       // dP of this lane's sample in row tile j: bins 8 h .. 8 h + 7
@@ -315,7 +322,15 @@ __global__ __launch_bounds__(512, 1) void k_gemm_bf16(GemmArgs a) {
 #pragma unroll
         for (int j = 0; j < 2; ++j)
           acc[1][i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(bp[i][4], dq[j], acc[1][i][j], 0, 0, 0);
+    };
+    int s = 0;
+    for (; s + kStages <= n_steps; s += kStages) {
+      step(s, 0);
+      step(s + 1, 1);
+      step(s + 2, 2);
+      step(s + 3, 3);
     }
+    for (; s < n_steps; ++s) step(s, s & (kStages - 1));
   };
   if (live[1]) run(std::integral_constant<int, 2>{});
   else run(std::integral_constant<int, 1>{});

@@ -624,9 +624,12 @@ gtod_status gtod_load_filters(gtod_ctx* c, const gtod_spectral_desc* d, int32_t*
   if (!c || !d || !id) return fail(c, GTOD_EINVAL, "NULL argument");
   const int F = d->F, K = d->K;
   if (F < 1 || K < 1 || d->n_pwv < 2) return fail(c, GTOD_EINVAL, "need F >= 1, K >= 1, n_pwv >= 2");
-  // the contraction addresses a response plane with 32-bit byte offsets
+  // the contractions address a response plane, and 256 panel rows, with
+  // 32-bit byte offsets
   if (round_up(F, kFPad) * round_up(K, kKPad) * 4 > (int64_t)UINT32_MAX)
     return fail(c, GTOD_EINVAL, "K x F too large: a padded response plane must stay below 4 GiB");
+  if (round_up(F, kFPad) * 256 * 4 > (int64_t)UINT32_MAX)
+    return fail(c, GTOD_EINVAL, "F too large: 256 padded panel rows must stay below 4 GiB");
   if (!d->nu_hz || !d->w_hz || !d->eta_z) return fail(c, GTOD_EINVAL, "NULL spectral array");
   if (!finite_pos(d->dpwv_mm) || !std::isfinite(d->pwv0_mm)) return fail(c, GTOD_EINVAL, "bad PWV axis");
   if (d->n_stage < 0 || (d->n_stage > 0 && !d->stages)) return fail(c, GTOD_EINVAL, "bad stage list");
