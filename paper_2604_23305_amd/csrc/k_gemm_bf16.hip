@@ -40,8 +40,14 @@
 // a barrier makes every wave's part of step s visible; the stage that step
 // s + 3 overwrites was last read before that barrier.
 //
-// Tile index -> workgroup mapping keeps the channel groups of one time tile
-// on the same XCD so the panel tile is fetched once into that XCD's L2.
+// The step loop is unrolled by the ring depth, so each step's stage is a
+// constant and its LDS reads take immediate offsets; DMA sources are
+// scalar base addresses plus 32-bit lane offsets.  The split of dP is the
+// only vector arithmetic besides the MFMAs.
+//
+// Tile index -> workgroup mapping: block b runs on XCD b mod 8, so the
+// channel groups of one time tile are given blocks of the same XCD and can
+// share the panel tile in its L2.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
