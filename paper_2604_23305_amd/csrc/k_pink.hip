@@ -207,8 +207,8 @@ __device__ __forceinline__ void stockham_pass(float2* buf, Addr addr, int lgL, i
 // In-place inverse DFTs (natural order in and out) of the 2^lgT
 // transforms of length 2^lgL (<= 4096) in buf.
 template <int EMAX, bool TFAST, class Addr>
-__device__ void fft_inv(float2* buf, Addr addr, int lgL, int lgT,
-                        const float2* __restrict__ tab) {
+__device__ __forceinline__ void fft_inv(float2* buf, Addr addr, int lgL, int lgT,
+                                        const float2* __restrict__ tab) {
   int lgNs = 0;
   while (lgL - lgNs >= 4) {
     stockham_pass<4, EMAX, TFAST>(buf, addr, lgL, lgT, lgNs, tab);
@@ -264,11 +264,14 @@ __global__ void k_pink_tables(float2* tab) {
 // once; every Z_k is built from X_k and X_{M-k} held in LDS, two at a time
 // (e^{2 pi i (M-k)/N} = -conj e^{2 pi i k/N}).
 // Dynamic LDS: one or two padded transforms of M2 values; EMAX bounds the
-// values per workgroup.
-template <int EMAX>
+// values per workgroup.  LGM2 > 0 fixes lg M2 at compile time (the length
+// every two-pass series uses), so that the transform's index arithmetic
+// folds into constants; LGM2 = 0 takes it from the arguments.
+template <int EMAX, int LGM2>
 __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
   extern __shared__ float2 buf[];
-  const AddrPadded at{a.lgM2};
+  const int lgM2 = LGM2 > 0 ? LGM2 : a.lgM2;
+  const AddrPadded at{lgM2};
   const int grp = blockIdx.x;
   const int sl = blockIdx.y;
   const int64_t series = a.s0 + sl;
@@ -277,8 +280,8 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
   const float sc = a.scale[k];
   const float halpha = -0.5f * a.alpha[k];
   const float fstep = (float)(a.fs / (double)a.N);
-  const int M1 = a.M1, M2 = a.M2;
-  const int lgN = a.lgM1 + a.lgM2 + 1;
+  const int M1 = a.M1, M2 = 1 << lgM2;
+  const int lgN = a.lgM1 + lgM2 + 1;
   // columns of this group: kind 0 = {0}, 1 = {M1/2}, 2 = {k1, M1 - k1}
   int kind, col[2], ncol;
   if (grp == 0) { kind = 0; col[0] = 0; ncol = 1; }
@@ -287,8 +290,8 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
   col[1] = (ncol == 2) ? col[1] : col[0];
 
   // draw X for every bin of the group's columns (natural order)
-  for (int idx = threadIdx.x; idx < (ncol << a.lgM2); idx += blockDim.x) {
-    const int c = idx >> a.lgM2, k2 = idx & (M2 - 1);
+  for (int idx = threadIdx.x; idx < (ncol << lgM2); idx += blockDim.x) {
+    const int c = idx >> lgM2, k2 = idx & (M2 - 1);
     const int64_t j = col[c] + (int64_t)M1 * k2;
     float2 x = make_float2(0.f, 0.f);
     if (j > 0 && j < a.M) {
@@ -341,8 +344,13 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
     }
   }
   __syncthreads();
-  fft_inv<EMAX, false>(buf, at, a.lgM2, ncol - 1, a.tab);
-  const int lgM = a.lgM1 + a.lgM2;
+  if constexpr (LGM2 > 0) {
+    if (ncol == 2) fft_inv<EMAX, false>(buf, at, LGM2, 1, a.tab);
+    else fft_inv<EMAX, false>(buf, at, LGM2, 0, a.tab);
+  } else {
+    fft_inv<EMAX, false>(buf, at, lgM2, ncol - 1, a.tab);
+  }
+  const int lgM = a.lgM1 + lgM2;
   for (int c = 0; c < ncol; ++c) {
     const int k1 = col[c];
     if (M1 == 1) {
@@ -394,10 +402,12 @@ void launch_pink_pass1(const PinkArgs& a, hipStream_t s) {
   const int e = (a.M1 == 1 ? 1 : 2) << a.lgM2;   // values per workgroup
   const size_t lds = (size_t)(e + (e >> 4)) * sizeof(float2);
   const dim3 grid(groups, a.n_series);
-  if (e <= kLdsC)
-    hipLaunchKernelGGL(k_pink_pass1<kLdsC>, grid, dim3(256), lds, s, a);
+  if (e <= kLdsC && a.lgM2 == kPinkLgM2)
+    hipLaunchKernelGGL((k_pink_pass1<kLdsC, kPinkLgM2>), grid, dim3(256), lds, s, a);
+  else if (e <= kLdsC)
+    hipLaunchKernelGGL((k_pink_pass1<kLdsC, 0>), grid, dim3(256), lds, s, a);
   else
-    hipLaunchKernelGGL(k_pink_pass1<2 * kLdsC>, grid, dim3(256), lds, s, a);
+    hipLaunchKernelGGL((k_pink_pass1<2 * kLdsC, 0>), grid, dim3(256), lds, s, a);
 }
 
 void launch_pink_pass2(const PinkArgs& a, hipStream_t s) {
