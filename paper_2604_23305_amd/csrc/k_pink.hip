@@ -370,23 +370,29 @@ __global__ __launch_bounds__(256) void k_pink_pass1(PinkArgs a) {
 // Pass 2 for at most EMAX = 2^(lgM1 + lgB2) elements per workgroup, held
 // in dynamic LDS of exactly that size (small blocks keep many workgroups
 // per CU, which is what this memory-bound pass needs).
-template <int EMAX>
+// LGM1 > 0 fixes lg M1 at compile time for series whose columns are
+// 2048 long (lg M2 = 11), so that the index arithmetic folds; LGM1 = 0
+// takes the lengths from the arguments.
+template <int EMAX, int LGM1>
 __global__ __launch_bounds__(256) void k_pink_pass2(PinkArgs a) {
   extern __shared__ float2 buf[];
   const int nb = blockIdx.x;
   const int sl = blockIdx.y;
   const int64_t series = a.s0 + sl;
-  const int M2 = a.M2, lgB2 = a.lgB2, B2 = 1 << lgB2;
+  constexpr int kLgB2 = LGM1 > 0 ? (12 - LGM1 < kPinkLgB2 ? 12 - LGM1 : kPinkLgB2) : 0;
+  const int lgM1 = LGM1 > 0 ? LGM1 : a.lgM1;
+  const int lgM2 = LGM1 > 0 ? kPinkLgM2 : a.lgM2;
+  const int M2 = 1 << lgM2, lgB2 = LGM1 > 0 ? kLgB2 : a.lgB2, B2 = 1 << lgB2;
   const int m20 = nb << lgB2;
-  const float2* src = a.scratch + ((int64_t)sl << (a.lgM1 + a.lgM2));
-  const int n = 1 << (a.lgM1 + lgB2);
+  const float2* src = a.scratch + ((int64_t)sl << (lgM1 + lgM2));
+  const int n = 1 << (lgM1 + lgB2);
   // element k1 of transform bb at k1 B2 + bb: both sides consecutive
   for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
     const int k1 = idx >> lgB2, bb = idx & (B2 - 1);
     buf[idx] = src[(int64_t)k1 * M2 + m20 + bb];
   }
   __syncthreads();
-  fft_inv<EMAX, true>(buf, AddrInterleaved{lgB2}, a.lgM1, lgB2, a.tab);
+  fft_inv<EMAX, true>(buf, AddrInterleaved{lgB2}, lgM1, lgB2, a.tab);
   for (int idx = threadIdx.x; idx < n; idx += blockDim.x) {
     const int m1 = idx >> lgB2, bb = idx & (B2 - 1);
     store_out(a, series, (int64_t)m1 * M2 + m20 + bb, buf[idx]);
@@ -414,10 +420,23 @@ void launch_pink_pass2(const PinkArgs& a, hipStream_t s) {
   const dim3 grid(a.M2 >> a.lgB2, a.n_series);
   const int e = 1 << (a.lgM1 + a.lgB2);
   const size_t lds = (size_t)e * sizeof(float2);
-  if (e <= kLdsC / 2)
-    hipLaunchKernelGGL(k_pink_pass2<kLdsC / 2>, grid, dim3(256), lds, s, a);
-  else
-    hipLaunchKernelGGL(k_pink_pass2<kLdsC>, grid, dim3(256), lds, s, a);
+#define GTOD_PASS2(EM, L) hipLaunchKernelGGL((k_pink_pass2<EM, L>), grid, dim3(256), lds, s, a)
+  if (a.lgM2 == kPinkLgM2 && a.lgB2 == std::min(kPinkLgB2, 12 - a.lgM1)) {
+    switch (a.lgM1) {   // e = 2^(lgM1 + lgB2) <= 4096
+      case 1: GTOD_PASS2(kLdsC / 2, 1); return;
+      case 2: GTOD_PASS2(kLdsC / 2, 2); return;
+      case 3: GTOD_PASS2(kLdsC / 2, 3); return;
+      case 4: GTOD_PASS2(kLdsC / 2, 4); return;
+      case 5: GTOD_PASS2(kLdsC / 2, 5); return;
+      case 6: GTOD_PASS2(kLdsC / 2, 6); return;
+      case 7: GTOD_PASS2(kLdsC / 2, 7); return;
+      case 8: GTOD_PASS2(kLdsC, 8); return;
+      default: break;
+    }
+  }
+  if (e <= kLdsC / 2) GTOD_PASS2(kLdsC / 2, 0);
+  else GTOD_PASS2(kLdsC, 0);
+#undef GTOD_PASS2
 }
 
 __global__ void k_philox(const uint32_t* ctr, uint32_t* out, int64_t n,
