@@ -14,7 +14,7 @@
 //
 // Workgroup: 4 waves along time, each 32 samples x both (or the one live)
 // 32-channel tiles of the group: 96 accumulator registers (AGPRs) beside
-// 116 VGPRs, and 60 KB of LDS, so two workgroups share a CU and one's
+// 120 VGPRs, and 60 KB of LDS, so two workgroups share a CU and one's
 // barriers and epilogue overlap the other's MFMAs.
 //
 // Operand staging: depth chunks of 16 frequency bins go straight from
@@ -33,6 +33,11 @@
 // LDS reads and for its DMAs of chunk c + 1, then passes the one barrier
 // of the chunk: chunk c + 1 is visible and no wave reads stage c mod 3
 // any more, which then takes chunk c + 3.
+// The chunk loop is unrolled by the ring depth, so stage addresses are
+// constants (LDS reads take immediate offsets), and DMA sources are scalar
+// base addresses plus 32-bit lane offsets: the loop's only vector
+// arithmetic besides the MFMAs is the dP^2 products, because vector
+// instructions in the MFMA stream cost matrix-core cycles.
 // Tile index -> workgroup mapping: block b runs on XCD b mod 8, so the
 // channel groups of one time tile are given blocks of the same XCD and
 // can share the panel tile in its L2.
