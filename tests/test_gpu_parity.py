@@ -528,15 +528,17 @@ def test_error_paths(ctx):
         g.free(tiny)
 
 
-def test_response_plane_of_4_gib_is_rejected(ctx):
-    """F x K whose padded response plane reaches 4 GiB (the contraction's
-    32-bit operand offsets) is refused before anything is allocated."""
-    F, K = 1 << 20, 1 << 10
+@pytest.mark.parametrize("F,K,why", [(1 << 20, 1 << 10, "response plane"),
+                                     ((1 << 22) + 1, 1, "panel rows")])
+def test_response_plane_of_4_gib_is_rejected(ctx, F, K, why):
+    """F x K whose padded response plane reaches 4 GiB, or F whose 256
+    padded panel rows do (the contractions' 32-bit operand offsets), is
+    refused before anything is allocated."""
     nu = np.linspace(200e9, 460e9, F)
     w = np.full(F, nu[1] - nu[0])
     eta_z = np.full((2, F), 0.9)
     f = np.linspace(210e9, 450e9, K)
-    with pytest.raises(g.GtodError, match="EINVAL"):
+    with pytest.raises(g.GtodError, match="EINVAL.*" + why):
         g.load_filters(ctx, nu, w, eta_z, 0.0, 1.0, 270.0, [], "lorentz",
                        f_hz=f, R=np.full(K, 500.0), eta_peak=np.full(K, 0.5))
 
