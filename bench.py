@@ -353,6 +353,12 @@ def elementwise(kern, workload, copy, sc):
         if name not in kern:
             continue
         gbs = kern[name]["alg_gbs"]
+        if name == "pink_pass2":
+            # the library counts 16 bytes per complex point (a scratch read
+            # and two TOD samples); the TOD keeps only t_total of the
+            # transform's N samples, so the store is 8 t_total / N bytes
+            n_fft = 1 << max(1, (sc.t_total - 1).bit_length())
+            gbs *= (8.0 + 8.0 * min(1.0, sc.t_total / n_fft)) / 16.0
         if name == "panel":
             k = kern[name]
             rows = k["alg_gbs"] * 1e9 * k["avg_ms"] / 1e3 / (20.0 * sc.F + 32.0)
