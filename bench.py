@@ -394,9 +394,9 @@ def kernel_table(prof):
     """Per-kernel figures from the library's event timing, with the
     algorithmic work the library reports per kernel (FLOP for the
     contractions, bytes for the panel and the reduction kernels, complex
-    points for the 1/f passes:
-    an 8-byte scratch write in pass 1; a scratch read plus the in-place add
-    into the TOD, 16 bytes, in pass 2)."""
+    points for the 1/f passes: an 8-byte scratch write in pass 1; a
+    scratch read plus two TOD samples, 16 bytes, in pass 2, which
+    `elementwise` scales to the TOD samples a series keeps)."""
     kern = {}
     for name, (ms, n, units) in prof.items():
         if n == 0:
